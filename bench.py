@@ -1,0 +1,228 @@
+#!/usr/bin/env python
+"""Benchmark of the space-time heat-equation solver on one MI355X.
+
+Metric: PCG unknowns x iterations per second, and time-to-solve at 1e-8
+relative residual (sqrt(r^T K_X r) relative to the first residual), for the
+single FP64 solve with N = 2^10 time intervals and h = 2^-9 (1025 x 261121 =
+267,649,025 unknowns; seeded Fourier forcing, u0 = sin(pi x) sin(pi y)).
+One step = one complete solve (right-hand side, f-hat, PCG, u = W w) with
+the data already resident on the GPU.  The FP32-mixed form of the same solve
+is timed beside it.
+
+Prints one JSON line.  Only one GPU is used; --gpus > 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+WORKLOADS = {
+    # name: (J, K, nrhs, g seed, u0 kind)
+    "heat2d_J10_K9": (10, 9, 1, 2, "sin"),
+    "heat2d_J12_K9": (12, 9, 1, 2, "sin"),
+    "heat2d_J8_K7_B64": (8, 7, 64, 1000, "random4"),
+    "heat2d_J4_K4": (4, 4, 1, None, "sin"),
+}
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="heat2d_J10_K9", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-compare", action="store_true", help="skip the other-precision run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-seconds", type=float, default=20.0)
+    return ap.parse_args()
+
+
+def load_inputs(stp, ctx, J, K, nrhs, seed, u0kind, torch):
+    import synth
+
+    dev = torch.device("cuda:0")
+    for b in range(nrhs):
+        if seed is None:
+            stp.stp_set_g(ctx, b, None)
+        else:
+            g = synth.fourier_g_torch(J, K, seed + b if nrhs > 1 else seed, dev)
+            stp.stp_set_g(ctx, b, g.reshape(-1))
+            del g
+        if u0kind == "sin":
+            u0 = synth.sine_product(K, 1, 1)
+        else:
+            u0 = synth.smooth_u0(K, seed + b)
+        stp.stp_set_u0(ctx, b, u0.reshape(-1).copy())
+    torch.cuda.synchronize()
+
+
+def run_solves(stp, ctx, nrhs, tol, steps, warmup, torch, profile=False):
+    for _ in range(warmup):
+        stp.stp_solve(ctx, tol, nrhs)
+    torch.cuda.synchronize()
+    if profile:
+        stp.stp_profile(ctx, True)
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        status, st = stp.stp_solve(ctx, tol, nrhs)
+        stats.append(st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kstats = None
+    if profile:
+        kstats = {k: stp.stp_profile_read(ctx, k) for k in stp.STP_KERNEL_NAMES}
+        stp.stp_profile(ctx, False)
+    return (t1 - t0) / steps, stats, kstats
+
+
+def cpu_baseline(seconds_budget):
+    """The oracle (NumPy FP64, unmodified) on a bounded sample of the workload:
+    PCG on the same mesh (h = 2^-9) with 2^1 + 1 time rows, seeded Fourier
+    forcing, as many iterations as fit in the budget (at least one)."""
+    import numpy as np
+
+    import oracle
+    import synth
+    from oracle.pcg import pcg
+    from oracle.schur import Problem
+
+    J, K = 1, 9
+    P = Problem(J, K)
+    g = synth.fourier_g(J, K, 2)
+    u0 = synth.sine_product(K, 1, 1)
+    t0 = time.perf_counter()
+    fhat = P.WT(P.rhs(g, u0))
+    t_rhs = time.perf_counter() - t0
+    its = 0
+    t0 = time.perf_counter()
+    # one iteration to size the run, then more while within the budget
+    w, k, _ = pcg(P, fhat, tol=0.0, maxit=1)
+    t1 = time.perf_counter() - t0
+    per_it = t1
+    more = max(0, int((seconds_budget - t_rhs - t1) / max(per_it, 1e-9)) - 1)
+    its = 1
+    if more > 0:
+        t0 = time.perf_counter()
+        w, k, _ = pcg(P, fhat, tol=0.0, maxit=1 + more)
+        t1 = time.perf_counter() - t0
+        its = 1 + more
+    unknowns = (2 ** J + 1) * (2 ** K - 1) ** 2
+    threads = 1  # NumPy elementwise kernels run on one thread
+    return {
+        "value": unknowns * its / t1,
+        "unit": "unknowns*iters/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"oracle PCG (NumPy FP64) on h=2^-9 with {2 ** J + 1} time rows "
+                   f"({unknowns} unknowns), {its} iterations in {t1:.1f} s; rhs+f-hat "
+                   f"{t_rhs:.1f} s not counted; host cores available {os.cpu_count()}"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU time "
+              "sharding is not part of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2009_08875_amd as stp
+
+    J, K, nrhs, seed, u0kind = WORKLOADS[args.workload]
+    prec = stp.STP_FP64 if args.precision == "fp64" else stp.STP_MIXED
+    unknowns = (2 ** J + 1) * (2 ** K - 1) ** 2 * nrhs
+    print(f"# workload {args.workload} J={J} K={K} nrhs={nrhs} precision={args.precision}",
+          file=sys.stderr, flush=True)
+
+    ctx = stp.stp_create(J, K, nrhs, prec, stream=torch.cuda.current_stream())
+    load_inputs(stp, ctx, J, K, nrhs, seed, u0kind, torch)
+    t_step, stats, kst = run_solves(stp, ctx, nrhs, args.tol, args.steps, args.warmup, torch,
+                                    profile=True)
+    its = stats[-1][0]["iterations"]
+    iters_sum = sum(s["iterations"] for s in stats[-1])
+    u_main = None
+    if not args.no_compare:
+        u_main = torch.zeros(unknowns // nrhs, dtype=torch.float64, device="cuda:0")
+        stp.stp_get_solution(ctx, 0, u_main)
+    stp.stp_destroy(ctx)
+    print(f"# main: {t_step * 1e3:.1f} ms per solve, iterations {its}", file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel (largest summed device time)
+    dom = max(kst, key=lambda k: kst[k]["total_ms"])
+    d = kst[dom]
+    avg_ms = d["total_ms"] / max(d["launches"], 1)
+    bytes_per_launch = d["alg_bytes"] / max(d["launches"], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    roofline = {
+        "kernel": stp.STP_KERNEL_NAMES[dom],
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "avg_launch_ms": round(avg_ms, 4),
+        "alg_bytes_per_launch": bytes_per_launch,
+        "launches": d["launches"],
+    }
+
+    compare = None
+    if not args.no_compare:
+        other = stp.STP_MIXED if prec == stp.STP_FP64 else stp.STP_FP64
+        ctx = stp.stp_create(J, K, nrhs, other, stream=torch.cuda.current_stream())
+        load_inputs(stp, ctx, J, K, nrhs, seed, u0kind, torch)
+        t2, st2, _ = run_solves(stp, ctx, nrhs, args.tol, 1, 1, torch)
+        u2 = torch.zeros_like(u_main)
+        stp.stp_get_solution(ctx, 0, u2)
+        torch.cuda.synchronize()
+        diff = (torch.linalg.vector_norm(u2 - u_main) / torch.linalg.vector_norm(u_main)).item()
+        stp.stp_destroy(ctx)
+        compare = {
+            "precision": "mixed" if other == stp.STP_MIXED else "fp64",
+            "time_to_solve_s": round(t2, 4),
+            "inner_iterations": st2[-1][0]["iterations"],
+            "outer_iterations": st2[-1][0]["outer_iterations"],
+            "unknowns_iters_per_s": unknowns * st2[-1][0]["iterations"] / t2,
+            "speedup_time_to_solve": round(t_step / t2, 3),
+            "rel_l2_diff_vs_main": diff,
+        }
+        print(f"# compare: {compare}", file=sys.stderr, flush=True)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_sample_seconds)
+
+    line = {
+        "metric": "PCG unknowns*iters/s (time-to-solve at 1e-8 rel res; FP32-mixed vs FP64)",
+        "value": unknowns * iters_sum / nrhs * nrhs / t_step if nrhs > 1 else unknowns * its / t_step,
+        "unit": "unknowns*iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_step * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == stp.STP_FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "J": J, "K": K, "nrhs": nrhs,
+                   "unknowns": unknowns, "precision": args.precision, "rel_tol": args.tol,
+                   "iterations": its, "time_to_solve_s": round(t_step, 4),
+                   "parallelism": "single-gpu"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "compare": compare,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

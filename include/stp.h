@@ -1,0 +1,153 @@
+/*
+ * stp.h -- C-ABI of the space-time parabolic solver for MI355X (gfx950).
+ *
+ * The library solves the space-time discretisation of the heat equation
+ *     du/dt - Laplace(u) = g  on (0,1)^2 x (0,1),  u = 0 on the boundary,  u(0) = u0
+ * by the method of van Venetie & Westerdiep, "A parallel algorithm for solving
+ * linear parabolic evolution equations" (arXiv 2009.08875):
+ *   - trial space: continuous piecewise linears in time (N = 2^J uniform
+ *     intervals) times P1 finite elements on the uniform 2^K x 2^K square mesh
+ *     cut along its "/" diagonals (Section 4, Section 5.1);
+ *   - the Schur-complement system S u = f of eq. (m9), written as in Lemma 4.2
+ *     with K_x = two symmetric multigrid V-cycles for A_x (Section 3.1, 5.1);
+ *   - PCG on the wavelet-in-time system S-hat w = f-hat, S-hat = W^T S W, with
+ *     the block-diagonal preconditioner K_X of Theorem 3.1 (alpha = 0.3), and
+ *     u = W w (Section 3.3, Section 3.4).
+ *
+ * Conventions (every entry point):
+ *   - Arrays are FP64, time-major: a space-time array holds (2^J + 1) rows of
+ *     N_x = (2^K - 1)^2 values; row i is the nodal vector at t_i = i / 2^J, and
+ *     node (x_a, y_b) = (a h, b h), 1 <= a, b <= 2^K - 1, h = 2^-K, sits at
+ *     offset (b - 1)(2^K - 1) + (a - 1).  Boundary values are zero and omitted.
+ *   - on_device = 0: the pointer is host memory; it is read or written before
+ *     the call returns.  on_device = 1: the pointer is device memory on the
+ *     context's device; it is read or written in order on the context's stream,
+ *     so the caller keeps it alive until that stream has been synchronised.
+ *   - The caller owns every buffer it passes; the library owns every device
+ *     allocation made inside a context or server.
+ *   - Every function returns stp_status (0 = STP_OK) and never throws.  A
+ *     positive status is a warning; a negative one an error.  stp_last_error()
+ *     gives a readable description of the calling thread's last failure.
+ *     After STP_E_DEVICE the context must be destroyed.
+ */
+#ifndef STP_H
+#define STP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int stp_status;
+#define STP_OK                 0
+#define STP_NOT_CONVERGED      1   /* maxit reached; the iterate is readable */
+#define STP_E_INVALID_ARG     -1   /* argument out of range, NULL where required, wrong state */
+#define STP_E_OUT_OF_MEMORY   -2   /* device allocation failed or budget exceeded */
+#define STP_E_BREAKDOWN       -3   /* PCG breakdown: p^T S-hat p <= 0 or a non-finite scalar */
+#define STP_E_DEVICE          -4   /* a HIP call failed; the context is unusable */
+#define STP_E_UNSUPPORTED     -5   /* valid request this build does not handle */
+#define STP_E_BUSY            -6   /* server: result not ready yet */
+
+typedef enum {
+  STP_FP64 = 0,   /* FP64 storage and arithmetic throughout */
+  STP_MIXED = 1   /* FP32 inner PCG (storage and arithmetic of every operator),
+                     FP64 dot products and scalars, FP64 outer residual
+                     f-hat - S-hat w and FP64 refinement w += d */
+} stp_precision;
+
+/* Options; a zero-initialised struct selects the paper's settings
+ * (Section 5.1, Section 5.2): alpha = 0.3, 2 V-cycles, 3 smoothing steps. */
+typedef struct {
+  double alpha;      /* alpha in K_j = (alpha A_x + 2^j M_x)^{-1}; 0 -> 0.3 */
+  int vcycles;       /* V-cycles per multigrid application; 0 -> 2 */
+  int sweeps;        /* Gauss-Seidel steps before and after the coarse grid; 0 -> 3 */
+  int maxit;         /* PCG iteration limit (inner limit in STP_MIXED); 0 -> 200 */
+  double inner_tol;  /* STP_MIXED: relative reduction per inner solve; 0 -> 1e-4 */
+  int max_outer;     /* STP_MIXED: refinement-step limit; 0 -> 20 */
+} stp_options;
+
+typedef struct {
+  int iterations;        /* S-hat applications of the (inner) PCG, summed */
+  int outer_iterations;  /* STP_MIXED: FP64 residual evaluations (0 for STP_FP64) */
+  double rel_residual;   /* sqrt(r^T K_X r / f-hat^T K_X f-hat) at exit */
+  double seconds;        /* device time of the solve (HIP events on the stream) */
+  int status;            /* per right-hand side: STP_OK, STP_NOT_CONVERGED, STP_E_BREAKDOWN */
+} stp_stats;
+
+typedef struct stp_ctx stp_ctx;
+
+/* Create a solver for N = 2^J time intervals (0 <= J <= 14), a 2^K x 2^K
+ * mesh (1 <= K <= 10) and nrhs >= 1 independent right-hand sides sharing the
+ * mesh, solved together (one launch per operator covers all of them).
+ * hip_stream: a hipStream_t to run on (NULL = the library creates its own).
+ * Allocates all device memory of the context; STP_E_OUT_OF_MEMORY if it does
+ * not fit.  u0 and g start at zero. */
+stp_status stp_create(int J, int K, int nrhs, int precision, const stp_options* opt,
+                      void* hip_stream, stp_ctx** out);
+
+/* u0: N_x values for right-hand side `rhs` (nodal interpolant, Lemma 4.1's u_0). */
+stp_status stp_set_u0(stp_ctx* ctx, int rhs, const double* u0, int on_device);
+
+/* g: (2^J + 1) x N_x nodal values of the forcing for right-hand side `rhs`;
+ * NULL sets g = 0.  The data are interpolated (continuous piecewise linear in
+ * time, P1 in space) and integrated exactly (Lemma 4.1's g). */
+stp_status stp_set_g(stp_ctx* ctx, int rhs, const double* g, int on_device);
+
+/* Solve every right-hand side to sqrt(r^T K_X r) <= rel_tol sqrt(f-hat^T K_X f-hat)
+ * (r = f-hat - S-hat w, w_0 = 0; the quantity of eq. (stopping)).  rel_tol = 0
+ * runs exactly maxit iterations.  per_rhs (may be NULL) receives nrhs entries.
+ * Returns STP_OK, STP_NOT_CONVERGED (some rhs hit maxit), STP_E_BREAKDOWN. */
+stp_status stp_solve(stp_ctx* ctx, double rel_tol, stp_stats* per_rhs);
+
+/* u = W w of the last solve: (2^J + 1) x N_x nodal values. */
+stp_status stp_get_solution(stp_ctx* ctx, int rhs, double* u, int on_device);
+stp_status stp_get_iterations(const stp_ctx* ctx, int rhs, int* iterations);
+
+/* Device bytes held by a context with these sizes (planning / admission). */
+stp_status stp_footprint(int J, int K, int nrhs, int precision, size_t* bytes);
+
+void stp_destroy(stp_ctx* ctx);
+
+const char* stp_status_string(stp_status s);
+const char* stp_last_error(void);
+
+/* ---- single operators, for parity checks of each step -------------------
+ * stp_apply reads `in` and writes `out`, both (2^J + 1) x N_x FP64 arrays of
+ * right-hand side `rhs`, using the kernels of precision `precision`
+ * (STP_MIXED = the FP32 kernels: the input is rounded to FP32, the result
+ * widened to FP64).  The operators are:                                     */
+#define STP_OP_W       0  /* synthesis W_t (x) Id: wavelet -> nodal (Section 3.3) */
+#define STP_OP_WT      1  /* analysis (W_t (x) Id)^T                              */
+#define STP_OP_S       2  /* S of Lemma 4.2 (nodal)                               */
+#define STP_OP_SHAT    3  /* S-hat = W^T S W (eq. (schur-mat))                    */
+#define STP_OP_KX      4  /* K_X of Theorem 3.1 on wavelet coordinates           */
+#define STP_OP_KSPACE  5  /* K_x (two V-cycles for A_x) on every time row         */
+#define STP_OP_RHS     6  /* f of Lemma 4.1 from the context's g and u0; `in` unused */
+#define STP_OP_A       7  /* A_x on every time row                                */
+#define STP_OP_M       8  /* M_x on every time row                                */
+stp_status stp_apply(stp_ctx* ctx, int op, int precision, int rhs,
+                     const double* in, double* out, int on_device);
+
+/* ---- kernel timing, for roofline reports ------------------------------
+ * While enabled, the library brackets every launch of its hot kernels with
+ * HIP events on the context stream and accumulates, per kernel, the number
+ * of launches, their summed device time and their algorithmic HBM bytes
+ * (each input element read once, each output element written once).
+ * Kernels: STP_KERNEL_MG_PRE and STP_KERNEL_MG_POST on the finest grid. */
+#define STP_KERNEL_MG_PRE   0
+#define STP_KERNEL_MG_POST  1
+#define STP_KERNEL_COUNT    2
+typedef struct {
+  int launches;
+  double total_ms;
+  double alg_bytes;   /* summed over the launches */
+} stp_kernel_stat;
+stp_status stp_profile(stp_ctx* ctx, int enable);          /* enabling also clears */
+stp_status stp_profile_read(stp_ctx* ctx, int kernel, stp_kernel_stat* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STP_H */

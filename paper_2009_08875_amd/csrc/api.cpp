@@ -1,0 +1,867 @@
+// C-ABI of the solver and its host-side driver: memory planning, the
+// multigrid cycle schedule, the operators S, S-hat, K_X and f as launch
+// sequences, and PCG (FP64, and FP32-inner / FP64-outer refinement).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "solver.h"
+
+using namespace stp;
+
+namespace stp {
+
+namespace {
+thread_local std::string g_last_error;
+constexpr double kDefaultAlpha = 0.3;   // Section 5.1
+constexpr int kMaxGridY = 65535;
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace stp
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                         \
+      return STP_E_DEVICE;                                                                  \
+    }                                                                                       \
+  } while (0)
+
+#define STP_TRY(expr)                       \
+  do {                                      \
+    stp_status s_ = (expr);                 \
+    if (s_ < 0) return s_;                  \
+  } while (0)
+
+namespace {
+
+stp_options resolve(const stp_options* o) {
+  stp_options r{};
+  if (o) r = *o;
+  if (r.alpha <= 0.0) r.alpha = kDefaultAlpha;
+  if (r.vcycles <= 0) r.vcycles = 2;
+  if (r.sweeps <= 0) r.sweeps = 3;
+  if (r.maxit <= 0) r.maxit = 200;
+  if (r.inner_tol <= 0.0) r.inner_tol = 1e-4;
+  if (r.max_outer <= 0) r.max_outer = 20;
+  return r;
+}
+
+// ------------------------------------------------------------ memory plan
+//
+// Every device allocation of a context goes through Arena so that the same
+// code computes the footprint (dry run) and allocates.
+struct Arena {
+  bool dry = true;
+  size_t bytes = 0;
+  std::vector<void*>* list = nullptr;
+  template <typename T>
+  stp_status get(T** p, int64_t count) {
+    size_t b = ((size_t)count * sizeof(T) + 511) & ~(size_t)511;
+    bytes += b;
+    if (dry) {
+      *p = nullptr;
+      return STP_OK;
+    }
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, b);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("hipMalloc of " + std::to_string(b) + " bytes failed: " + hipGetErrorString(e));
+      return STP_E_OUT_OF_MEMORY;
+    }
+    list->push_back(q);
+    e = hipMemset(q, 0, b);
+    if (e != hipSuccess) {
+      set_error(std::string("hipMemset: ") + hipGetErrorString(e));
+      return STP_E_DEVICE;
+    }
+    *p = (T*)q;
+    return STP_OK;
+  }
+};
+
+template <typename T>
+stp_status plan_mg(Arena& ar, MgScratch<T>& mg, int K, int64_t chunk_rows) {
+  mg.K = K;
+  mg.chunk_rows = chunk_rows;
+  STP_TRY(ar.get(&mg.xb[K], chunk_rows * slab_elems(K)));
+  for (int l = 1; l < K; ++l) {
+    STP_TRY(ar.get(&mg.xa[l], chunk_rows * slab_elems(l)));
+    STP_TRY(ar.get(&mg.xb[l], chunk_rows * slab_elems(l)));
+    STP_TRY(ar.get(&mg.b[l], chunk_rows * slab_elems(l)));
+  }
+  return STP_OK;
+}
+
+template <typename T>
+stp_status plan_ops(Arena& ar, Ops<T>& o, int K, int64_t rows, int64_t vec) {
+  STP_TRY(ar.get(&o.X, vec));
+  STP_TRY(ar.get(&o.y, 2 * vec));
+  STP_TRY(ar.get(&o.z, 2 * vec));
+  STP_TRY(plan_mg(ar, o.mg, K, std::min<int64_t>(rows, kMaxGridY)));
+  o.ready = !ar.dry;
+  return STP_OK;
+}
+
+template <typename T>
+stp_status plan_pcg(Arena& ar, PcgVecs<T>& v, int64_t vec, bool with_rhs) {
+  STP_TRY(ar.get(&v.w, vec));
+  STP_TRY(ar.get(&v.r, vec));
+  STP_TRY(ar.get(&v.z, vec));
+  STP_TRY(ar.get(&v.p, vec));
+  STP_TRY(ar.get(&v.q, vec));
+  if (with_rhs) STP_TRY(ar.get(&v.rhs, vec));
+  v.ready = !ar.dry;
+  return STP_OK;
+}
+
+stp_status plan_context(Arena& ar, stp_ctx* c) {
+  const int64_t vec = c->vec;
+  STP_TRY(ar.get(&c->g, vec));
+  STP_TRY(ar.get(&c->u0, (int64_t)c->nrhs * c->slab));
+  STP_TRY(ar.get(&c->fhat, vec));
+  STP_TRY(ar.get(&c->u, vec));
+  STP_TRY(ar.get(&c->sigma, c->rows));
+  STP_TRY(ar.get(&c->partials, (int64_t)c->nrhs * 1024));
+  STP_TRY(ar.get(&c->dots, c->nrhs));
+  STP_TRY(ar.get(&c->sc.rho, c->nrhs));
+  STP_TRY(ar.get(&c->sc.rho0, c->nrhs));
+  STP_TRY(ar.get(&c->sc.pq, c->nrhs));
+  STP_TRY(ar.get(&c->sc.rhonew, c->nrhs));
+  STP_TRY(ar.get(&c->sc.gamma, c->nrhs));
+  STP_TRY(ar.get(&c->sc.beta, c->nrhs));
+  STP_TRY(ar.get(&c->sc.target, c->nrhs));
+  STP_TRY(ar.get(&c->sc.active, c->nrhs));
+  STP_TRY(ar.get(&c->sc.its, c->nrhs));
+  STP_TRY(ar.get(&c->sc.status, c->nrhs));
+  STP_TRY(plan_ops(ar, c->ops64, c->K, c->rows, vec));
+  if (c->prec == STP_FP64) {
+    STP_TRY(plan_pcg(ar, c->pcg64, vec, false));
+  } else {
+    STP_TRY(ar.get(&c->w64, vec));
+    STP_TRY(ar.get(&c->r64, vec));
+    STP_TRY(plan_ops(ar, c->ops32, c->K, c->rows, vec));
+    STP_TRY(plan_pcg(ar, c->pcg32, vec, true));
+  }
+  return STP_OK;
+}
+
+void free_all(stp_ctx* c) {
+  for (auto& t : c->timed) {
+    c->ev_pool.push_back(t.a);
+    c->ev_pool.push_back(t.b);
+  }
+  c->timed.clear();
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  c->ev_pool.clear();
+  for (void* p : c->allocations) (void)hipFree(p);
+  c->allocations.clear();
+  if (c->h_active) (void)hipHostFree(c->h_active);
+  if (c->h_buf) (void)hipHostFree(c->h_buf);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+}
+
+// ------------------------------------------------------------ operators
+
+template <typename T>
+Ops<T>& ops_of(stp_ctx* c);
+template <>
+Ops<double>& ops_of<double>(stp_ctx* c) { return c->ops64; }
+template <>
+Ops<float>& ops_of<float>(stp_ctx* c) { return c->ops32; }
+
+// ------------------------------------------------------------ kernel timing
+
+stp_status take_event(stp_ctx* c, hipEvent_t* e) {
+  if (!c->ev_pool.empty()) {
+    *e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return STP_OK;
+  }
+  HIP_TRY(hipEventCreate(e));
+  return STP_OK;
+}
+
+stp_status flush_timing(stp_ctx* c) {
+  for (auto& t : c->timed) {
+    HIP_TRY(hipEventSynchronize(t.b));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, t.a, t.b));
+    stp_kernel_stat& k = c->kstat[t.kernel];
+    k.launches += 1;
+    k.total_ms += ms;
+    k.alg_bytes += t.bytes;
+    c->ev_pool.push_back(t.a);
+    c->ev_pool.push_back(t.b);
+  }
+  c->timed.clear();
+  return STP_OK;
+}
+
+// Launch `f` (returning hipError_t); when profiling, bracket it with events.
+template <typename F>
+stp_status timed_launch(stp_ctx* c, int kernel, double bytes, F f) {
+  if (!c->profiling) {
+    HIP_TRY(f());
+    return STP_OK;
+  }
+  if (c->timed.size() >= 4096) STP_TRY(flush_timing(c));
+  stp_ctx::Timed t{};
+  STP_TRY(take_event(c, &t.a));
+  STP_TRY(take_event(c, &t.b));
+  t.kernel = kernel;
+  t.bytes = bytes;
+  HIP_TRY(hipEventRecord(t.a, c->stream));
+  HIP_TRY(f());
+  HIP_TRY(hipEventRecord(t.b, c->stream));
+  c->timed.push_back(t);
+  return STP_OK;
+}
+
+// x = K[a, sigma] b: `vcycles` V-cycles from zero on `rows` slabs of level K.
+template <typename T>
+stp_status mg_apply(stp_ctx* c, MgScratch<T>& mg, const T* b, T* x, int64_t rows, double a,
+                    const double* sigma) {
+  const int K = c->K;
+  const int64_t slab = slab_elems(K);
+  for (int64_t r0 = 0; r0 < rows; r0 += mg.chunk_rows) {
+    const int nr = (int)std::min<int64_t>(mg.chunk_rows, rows - r0);
+    const T* bb = b + r0 * slab;
+    T* xx = x + r0 * slab;
+    const double* sg = sigma ? sigma + r0 : nullptr;
+    if (K == 1) {
+      HIP_TRY(mg_coarsest<T>(c->stream, bb, xx, nr, a, sg));
+      continue;
+    }
+    // algorithmic bytes of the fine-level kernels: every input element read
+    // once, every output element written once (interior nodes only)
+    const double nodes = (double)nr * grid_n(K) * grid_n(K);
+    const double cnodes = (double)nr * grid_n(K - 1) * grid_n(K - 1);
+    for (int cyc = 0; cyc < c->opt.vcycles; ++cyc) {
+      const T* xin = cyc == 0 ? nullptr : xx;
+      const double pre_bytes = sizeof(T) * ((xin ? 3.0 : 2.0) * nodes + cnodes);
+      STP_TRY(timed_launch(c, STP_KERNEL_MG_PRE, pre_bytes, [&] {
+        return mg_pre<T>(c->stream, xin, bb, mg.xb[K], mg.b[K - 1], K, nr, a, sg);
+      }));
+      for (int l = K - 1; l >= 2; --l)
+        HIP_TRY(mg_pre<T>(c->stream, nullptr, mg.b[l], mg.xb[l], mg.b[l - 1], l, nr, a, sg));
+      HIP_TRY(mg_coarsest<T>(c->stream, mg.b[1], mg.xa[1], nr, a, sg));
+      for (int l = 2; l <= K - 1; ++l)
+        HIP_TRY(mg_post<T>(c->stream, mg.xb[l], mg.b[l], mg.xa[l - 1], mg.xa[l], l, nr, a, sg));
+      const double post_bytes = sizeof(T) * (3.0 * nodes + cnodes);
+      STP_TRY(timed_launch(c, STP_KERNEL_MG_POST, post_bytes, [&] {
+        return mg_post<T>(c->stream, mg.xb[K], bb, mg.xa[K - 1], xx, K, nr, a, sg);
+      }));
+    }
+  }
+  return STP_OK;
+}
+
+// out = S X (Lemma 4.2) for `nrhs` right-hand sides starting at X.
+template <typename T>
+stp_status S_apply(stp_ctx* c, Ops<T>& o, const T* X, T* out, int nrhs) {
+  const int64_t v = (int64_t)nrhs * c->per_rhs;
+  const int64_t rows = (int64_t)nrhs * c->rows_per;
+  T* y1 = o.y;
+  T* y2 = o.y + v;
+  T* z1 = o.z;
+  T* z2 = o.z + v;
+  HIP_TRY(time_stencil_pair<T>(c->stream, X, y1, y2, c->J, c->K, nrhs));
+  STP_TRY(mg_apply<T>(c, o.mg, y1, z1, rows, 1.0, nullptr));
+  STP_TRY(mg_apply<T>(c, o.mg, y2, z2, rows, 1.0, nullptr));
+  HIP_TRY(combine<T>(c->stream, z1, z2, X, c->per_rhs, out, c->J, c->K, nrhs));
+  return STP_OK;
+}
+
+// out = S-hat p = W^T S W p (eq. (schur-mat)).
+template <typename T>
+stp_status Shat_apply(stp_ctx* c, Ops<T>& o, const T* p, T* out, int nrhs) {
+  const int64_t v = (int64_t)nrhs * c->per_rhs;
+  HIP_TRY(copy<T>(c->stream, p, o.X, v));
+  HIP_TRY(wavelet<T>(c->stream, o.X, c->J, c->K, nrhs, true));
+  STP_TRY(S_apply<T>(c, o, o.X, out, nrhs));
+  HIP_TRY(wavelet<T>(c->stream, out, c->J, c->K, nrhs, false));
+  return STP_OK;
+}
+
+// z = K_X r: row i gets K_l A K_l r_i, K_l = MG for (alpha A + 2^l M) (Theorem 3.1).
+template <typename T>
+stp_status KX_apply(stp_ctx* c, Ops<T>& o, const T* r, T* z, int nrhs) {
+  const int64_t v = (int64_t)nrhs * c->per_rhs;
+  const int64_t rows = (int64_t)nrhs * c->rows_per;
+  T* t1 = o.y;
+  T* t2 = o.y + v;
+  STP_TRY(mg_apply<T>(c, o.mg, r, t1, rows, c->opt.alpha, c->sigma));
+  HIP_TRY(apply_A<T>(c->stream, t1, t2, c->K, (int)rows));
+  STP_TRY(mg_apply<T>(c, o.mg, t2, z, rows, c->opt.alpha, c->sigma));
+  return STP_OK;
+}
+
+// f of Lemma 4.1 (FP64): f_i = M K_x G1_i + A K_x G0_i + [i = 0] M u0.
+stp_status rhs_apply(stp_ctx* c, double* f) {
+  Ops<double>& o = c->ops64;
+  const int64_t v = c->vec;
+  bool any_g = false;
+  for (int b = 0; b < c->nrhs; ++b) any_g = any_g || c->has_g[b];
+  double* z1 = o.z;
+  double* z2 = o.z + v;
+  if (any_g) {
+    double* G1 = o.y;
+    double* G0 = o.y + v;
+    HIP_TRY(rhs_stencil_pair<double>(c->stream, c->g, G1, G0, c->J, c->K, c->nrhs));
+    STP_TRY(mg_apply<double>(c, o.mg, G1, z1, c->rows, 1.0, nullptr));
+    STP_TRY(mg_apply<double>(c, o.mg, G0, z2, c->rows, 1.0, nullptr));
+  } else {
+    HIP_TRY(hipMemsetAsync(z1, 0, sizeof(double) * 2 * v, c->stream));
+  }
+  HIP_TRY(combine<double>(c->stream, z1, z2, c->u0, c->slab, f, c->J, c->K, c->nrhs));
+  return STP_OK;
+}
+
+// ------------------------------------------------------------ PCG
+
+stp_status read_active(stp_ctx* c, bool& any) {
+  HIP_TRY(hipMemcpyAsync(c->h_active, c->sc.active, sizeof(int) * c->nrhs, hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  any = false;
+  for (int b = 0; b < c->nrhs; ++b) any = any || c->h_active[b];
+  return STP_OK;
+}
+
+// PCG on S-hat w = rhs (w_0 = 0) in type T (Section 3.4).  If `adjust` is
+// set, it is called after the start (rho0 known) to rewrite targets/active.
+template <typename T, typename Adjust>
+stp_status pcg_run(stp_ctx* c, PcgVecs<T>& v, const T* rhs, double tol, int maxit, Adjust adjust) {
+  Ops<T>& o = ops_of<T>(c);
+  const int nrhs = c->nrhs;
+  const int64_t n = c->per_rhs;
+  const int64_t vec = c->vec;
+  HIP_TRY(hipMemsetAsync(v.w, 0, sizeof(T) * vec, c->stream));
+  HIP_TRY(copy<T>(c->stream, rhs, v.r, vec));
+  STP_TRY(KX_apply<T>(c, o, v.r, v.z, nrhs));
+  HIP_TRY(dot<T>(c->stream, v.r, v.z, n, nrhs, c->partials, c->sc.rhonew));
+  HIP_TRY(pcg_start(c->stream, c->sc, nrhs, tol));
+  STP_TRY(adjust());
+  HIP_TRY(copy<T>(c->stream, v.z, v.p, vec));
+  for (int it = 0; it < maxit; ++it) {
+    bool any = false;
+    STP_TRY(read_active(c, any));
+    if (!any) break;
+    STP_TRY(Shat_apply<T>(c, o, v.p, v.q, nrhs));
+    HIP_TRY(dot<T>(c->stream, v.p, v.q, n, nrhs, c->partials, c->sc.pq));
+    HIP_TRY(pcg_gamma(c->stream, c->sc, nrhs));
+    HIP_TRY(update_wr<T>(c->stream, v.w, v.r, v.p, v.q, c->sc.gamma, n, nrhs));
+    STP_TRY(KX_apply<T>(c, o, v.r, v.z, nrhs));
+    HIP_TRY(dot<T>(c->stream, v.r, v.z, n, nrhs, c->partials, c->sc.rhonew));
+    HIP_TRY(pcg_beta(c->stream, c->sc, nrhs));
+    HIP_TRY(update_p<T>(c->stream, v.p, v.z, c->sc.beta, n, nrhs));
+  }
+  return STP_OK;
+}
+
+struct HostScalars {
+  std::vector<double> rho, rho0;
+  std::vector<int> its, status, active;
+};
+
+stp_status read_scalars(stp_ctx* c, HostScalars& h) {
+  const int nr = c->nrhs;
+  h.rho.resize(nr);
+  h.rho0.resize(nr);
+  h.its.resize(nr);
+  h.status.resize(nr);
+  h.active.resize(nr);
+  HIP_TRY(hipMemcpyAsync(h.rho.data(), c->sc.rho, sizeof(double) * nr, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(h.rho0.data(), c->sc.rho0, sizeof(double) * nr, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(h.its.data(), c->sc.its, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(h.status.data(), c->sc.status, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(h.active.data(), c->sc.active, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return STP_OK;
+}
+
+stp_status solve_fp64(stp_ctx* c, double tol) {
+  PcgVecs<double>& v = c->pcg64;
+  STP_TRY(pcg_run<double>(c, v, c->fhat, tol, c->opt.maxit, [] { return (stp_status)STP_OK; }));
+  HostScalars h;
+  STP_TRY(read_scalars(c, h));
+  for (int b = 0; b < c->nrhs; ++b) {
+    stp_stats& s = c->stats[b];
+    s.iterations = h.its[b];
+    s.outer_iterations = 0;
+    s.rel_residual = h.rho0[b] > 0 ? std::sqrt(std::max(h.rho[b], 0.0) / h.rho0[b]) : 0.0;
+    s.status = h.status[b] == -3 ? STP_E_BREAKDOWN
+               : (h.status[b] == 1 || (tol > 0 && s.rel_residual <= tol) || h.rho0[b] == 0.0)
+                   ? STP_OK
+                   : STP_NOT_CONVERGED;
+    if (tol == 0.0 && h.status[b] != -3) s.status = STP_OK;
+  }
+  HIP_TRY(copy<double>(c->stream, v.w, c->u, c->vec));
+  return STP_OK;
+}
+
+// FP32 inner PCG with FP64 outer residual and refinement (spec form (1)).
+stp_status solve_mixed(stp_ctx* c, double tol) {
+  const int nr = c->nrhs;
+  PcgVecs<float>& v = c->pcg32;
+  const int64_t vec = c->vec;
+  std::vector<double> rho0_first(nr, -1.0), last_rel(nr, 1.0);
+  std::vector<int> done(nr, 0), inner_its(nr, 0), outer(nr, 0), status(nr, STP_NOT_CONVERGED);
+  HIP_TRY(hipMemsetAsync(c->w64, 0, sizeof(double) * vec, c->stream));
+  HIP_TRY(copy<double>(c->stream, c->fhat, c->r64, vec));
+  std::vector<double> tgt(nr);
+  std::vector<int> act(nr);
+  for (int k = 0; k < c->opt.max_outer; ++k) {
+    if (k > 0) {
+      STP_TRY(Shat_apply<double>(c, c->ops64, c->w64, c->r64, nr));
+      HIP_TRY(residual64(c->stream, c->fhat, c->r64, c->r64, vec));
+    }
+    HIP_TRY((cast<double, float>(c->stream, c->r64, v.rhs, vec)));
+    auto adjust = [&]() -> stp_status {
+      HostScalars h;
+      STP_TRY(read_scalars(c, h));
+      for (int b = 0; b < nr; ++b) {
+        if (done[b]) {
+          act[b] = 0;
+          tgt[b] = 0;
+          continue;
+        }
+        outer[b] = k;
+        if (k == 0) rho0_first[b] = h.rho0[b];
+        const double rel = rho0_first[b] > 0 ? std::sqrt(std::max(h.rho0[b], 0.0) / rho0_first[b]) : 0.0;
+        last_rel[b] = rel;
+        if (h.status[b] == -3) {
+          done[b] = 1;
+          status[b] = STP_E_BREAKDOWN;
+          act[b] = 0;
+        } else if (rho0_first[b] <= 0.0 || (tol > 0 && rel <= tol) || h.rho0[b] == 0.0) {
+          done[b] = 1;
+          status[b] = STP_OK;
+          act[b] = 0;
+        } else {
+          act[b] = 1;
+        }
+        // stop the inner solve at a relative reduction of inner_tol, but not
+        // below what the outer tolerance still needs
+        const double s0 = std::sqrt(std::max(h.rho0[b], 0.0));
+        const double floor_abs = 0.5 * tol * std::sqrt(std::max(rho0_first[b], 0.0));
+        tgt[b] = std::max(c->opt.inner_tol * s0, floor_abs);
+      }
+      HIP_TRY(hipMemcpyAsync(c->sc.target, tgt.data(), sizeof(double) * nr, hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(hipMemcpyAsync(c->sc.active, act.data(), sizeof(int) * nr, hipMemcpyHostToDevice, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      return STP_OK;
+    };
+    STP_TRY(pcg_run<float>(c, v, v.rhs, 0.0, c->opt.maxit, adjust));
+    HostScalars h;
+    STP_TRY(read_scalars(c, h));
+    bool all_done = true;
+    for (int b = 0; b < nr; ++b) {
+      if (!done[b]) {
+        inner_its[b] += h.its[b];
+        if (h.status[b] == -3) {
+          done[b] = 1;
+          status[b] = STP_E_BREAKDOWN;
+        }
+      }
+      all_done = all_done && done[b];
+    }
+    if (all_done) break;
+    HIP_TRY(add_correction(c->stream, c->w64, v.w, vec));
+  }
+  for (int b = 0; b < nr; ++b) {
+    stp_stats& s = c->stats[b];
+    s.iterations = inner_its[b];
+    s.outer_iterations = outer[b] + 1;
+    s.rel_residual = last_rel[b];
+    s.status = done[b] ? status[b] : STP_NOT_CONVERGED;
+  }
+  HIP_TRY(copy<double>(c->stream, c->w64, c->u, vec));
+  return STP_OK;
+}
+
+template <typename T>
+stp_status ensure_ops(stp_ctx* c, Ops<T>& o) {
+  if (o.ready) return STP_OK;
+  Arena ar;
+  ar.dry = false;
+  ar.list = &c->allocations;
+  STP_TRY(plan_ops(ar, o, c->K, c->rows, c->vec));
+  c->bytes += ar.bytes;
+  return STP_OK;
+}
+
+stp_status check_ctx(const stp_ctx* c) {
+  if (!c) {
+    set_error("NULL context");
+    return STP_E_INVALID_ARG;
+  }
+  return STP_OK;
+}
+
+stp_status check_rhs(const stp_ctx* c, int rhs) {
+  STP_TRY(check_ctx(c));
+  if (rhs < 0 || rhs >= c->nrhs) {
+    set_error("rhs index " + std::to_string(rhs) + " out of range [0, " + std::to_string(c->nrhs) + ")");
+    return STP_E_INVALID_ARG;
+  }
+  return STP_OK;
+}
+
+stp_status check_sizes(int J, int K, int nrhs, int precision) {
+  if (J < 0 || J > kMaxJ || K < 1 || K > kMaxK || nrhs < 1 || nrhs > 4096 ||
+      (precision != STP_FP64 && precision != STP_MIXED)) {
+    set_error("need 0 <= J <= 14, 1 <= K <= 10, 1 <= nrhs <= 4096 and a valid precision");
+    return STP_E_INVALID_ARG;
+  }
+  return STP_OK;
+}
+
+void init_dims(stp_ctx* c, int J, int K, int nrhs, int precision) {
+  c->J = J;
+  c->K = K;
+  c->nrhs = nrhs;
+  c->prec = precision;
+  c->slab = slab_elems(K);
+  c->rows_per = (1 << J) + 1;
+  c->rows = (int64_t)nrhs * c->rows_per;
+  c->per_rhs = c->rows_per * c->slab;
+  c->vec = c->rows * c->slab;
+}
+
+// copy `count` FP64 values (host or device) into a device scratch buffer
+stp_status stage_in(stp_ctx* c, const double* src, int on_device, int64_t count, double* dst) {
+  HIP_TRY(hipMemcpyAsync(dst, src, sizeof(double) * count,
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  if (!on_device) HIP_TRY(hipStreamSynchronize(c->stream));
+  return STP_OK;
+}
+
+}  // namespace
+
+// ================================================================== C-ABI
+
+extern "C" {
+
+const char* stp_status_string(stp_status s) {
+  switch (s) {
+    case STP_OK: return "ok";
+    case STP_NOT_CONVERGED: return "not converged (maxit reached)";
+    case STP_E_INVALID_ARG: return "invalid argument";
+    case STP_E_OUT_OF_MEMORY: return "out of device memory";
+    case STP_E_BREAKDOWN: return "PCG breakdown";
+    case STP_E_DEVICE: return "HIP device error";
+    case STP_E_UNSUPPORTED: return "unsupported";
+    case STP_E_BUSY: return "not ready";
+    default: return "unknown status";
+  }
+}
+
+const char* stp_last_error(void) { return g_last_error.c_str(); }
+
+stp_status stp_footprint(int J, int K, int nrhs, int precision, size_t* bytes) {
+  STP_TRY(check_sizes(J, K, nrhs, precision));
+  if (!bytes) {
+    set_error("NULL output");
+    return STP_E_INVALID_ARG;
+  }
+  stp_ctx c;
+  init_dims(&c, J, K, nrhs, precision);
+  Arena ar;
+  ar.dry = true;
+  STP_TRY(plan_context(ar, &c));
+  *bytes = ar.bytes;
+  return STP_OK;
+}
+
+stp_status stp_create(int J, int K, int nrhs, int precision, const stp_options* opt,
+                      void* hip_stream, stp_ctx** out) {
+  if (!out) {
+    set_error("NULL output");
+    return STP_E_INVALID_ARG;
+  }
+  *out = nullptr;
+  STP_TRY(check_sizes(J, K, nrhs, precision));
+  stp_options o = resolve(opt);
+  if (o.sweeps != 3) {
+    set_error("the GPU kernels implement 3 Gauss-Seidel steps per grid (sweeps = 3)");
+    return STP_E_UNSUPPORTED;
+  }
+  stp_ctx* c = new (std::nothrow) stp_ctx();
+  if (!c) {
+    set_error("host allocation failed");
+    return STP_E_OUT_OF_MEMORY;
+  }
+  init_dims(c, J, K, nrhs, precision);
+  c->opt = o;
+  c->has_g.assign(nrhs, 0);
+  c->iters.assign(nrhs, 0);
+  c->stats.assign(nrhs, stp_stats{});
+  auto fail = [&](stp_status s) {
+    free_all(c);
+    delete c;
+    return s;
+  };
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    set_error("no HIP device");
+    return fail(STP_E_DEVICE);
+  }
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) {
+      set_error("hipStreamCreate failed");
+      return fail(STP_E_DEVICE);
+    }
+    c->own_stream = true;
+  }
+  Arena ar;
+  ar.dry = false;
+  ar.list = &c->allocations;
+  stp_status st = plan_context(ar, c);
+  if (st < 0) return fail(st);
+  c->bytes = ar.bytes;
+  if (hipHostMalloc((void**)&c->h_active, sizeof(int) * nrhs) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_buf, sizeof(double) * 4 * nrhs) != hipSuccess ||
+      hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    set_error("pinned host allocation or event creation failed");
+    return fail(STP_E_DEVICE);
+  }
+  if (fill_level_sigma(c->stream, c->sigma, J, nrhs) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    set_error("initialisation kernels failed");
+    return fail(STP_E_DEVICE);
+  }
+  *out = c;
+  return STP_OK;
+}
+
+void stp_destroy(stp_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+}
+
+stp_status stp_set_u0(stp_ctx* c, int rhs, const double* u0, int on_device) {
+  STP_TRY(check_rhs(c, rhs));
+  double* dst = c->u0 + (int64_t)rhs * c->slab;
+  if (!u0) {
+    HIP_TRY(hipMemsetAsync(dst, 0, sizeof(double) * c->slab, c->stream));
+    return STP_OK;
+  }
+  const int64_t nn = (int64_t)grid_n(c->K) * grid_n(c->K);
+  double* tmp = c->ops64.z;  // compact staging area (large enough: >= vec elements)
+  STP_TRY(stage_in(c, u0, on_device, nn, tmp));
+  HIP_TRY(pack<double>(c->stream, tmp, dst, c->K, 1));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return STP_OK;
+}
+
+stp_status stp_set_g(stp_ctx* c, int rhs, const double* g, int on_device) {
+  STP_TRY(check_rhs(c, rhs));
+  double* dst = c->g + (int64_t)rhs * c->per_rhs;
+  if (!g) {
+    HIP_TRY(hipMemsetAsync(dst, 0, sizeof(double) * c->per_rhs, c->stream));
+    c->has_g[rhs] = 0;
+    return STP_OK;
+  }
+  const int64_t nn = (int64_t)grid_n(c->K) * grid_n(c->K);
+  double* tmp = c->ops64.z;
+  STP_TRY(stage_in(c, g, on_device, nn * c->rows_per, tmp));
+  HIP_TRY(pack<double>(c->stream, tmp, dst, c->K, (int)c->rows_per));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->has_g[rhs] = 1;
+  return STP_OK;
+}
+
+stp_status stp_solve(stp_ctx* c, double rel_tol, stp_stats* per_rhs) {
+  STP_TRY(check_ctx(c));
+  if (!(rel_tol >= 0.0) || rel_tol >= 1.0) {
+    set_error("rel_tol must be in [0, 1)");
+    return STP_E_INVALID_ARG;
+  }
+  HIP_TRY(hipEventRecord(c->ev0, c->stream));
+  STP_TRY(rhs_apply(c, c->fhat));
+  HIP_TRY(wavelet<double>(c->stream, c->fhat, c->J, c->K, c->nrhs, false));
+  if (c->prec == STP_FP64)
+    STP_TRY(solve_fp64(c, rel_tol));
+  else
+    STP_TRY(solve_mixed(c, rel_tol));
+  HIP_TRY(wavelet<double>(c->stream, c->u, c->J, c->K, c->nrhs, true));
+  HIP_TRY(hipEventRecord(c->ev1, c->stream));
+  HIP_TRY(hipEventSynchronize(c->ev1));
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  stp_status worst = STP_OK;
+  for (int b = 0; b < c->nrhs; ++b) {
+    c->stats[b].seconds = ms * 1e-3;
+    c->iters[b] = c->stats[b].iterations;
+    if (c->stats[b].status == STP_E_BREAKDOWN) worst = STP_E_BREAKDOWN;
+    else if (c->stats[b].status == STP_NOT_CONVERGED && worst == STP_OK) worst = STP_NOT_CONVERGED;
+    if (per_rhs) per_rhs[b] = c->stats[b];
+  }
+  c->solved = true;
+  if (worst == STP_E_BREAKDOWN) set_error("PCG breakdown (p^T S-hat p <= 0 or non-finite)");
+  return worst;
+}
+
+stp_status stp_get_solution(stp_ctx* c, int rhs, double* u, int on_device) {
+  STP_TRY(check_rhs(c, rhs));
+  if (!u) {
+    set_error("NULL output");
+    return STP_E_INVALID_ARG;
+  }
+  if (!c->solved) {
+    set_error("no solve has run on this context");
+    return STP_E_INVALID_ARG;
+  }
+  const int64_t nn = (int64_t)grid_n(c->K) * grid_n(c->K);
+  const int64_t count = nn * c->rows_per;
+  double* src = c->u + (int64_t)rhs * c->per_rhs;
+  if (on_device) {
+    HIP_TRY(unpack<double>(c->stream, src, u, c->K, (int)c->rows_per));
+  } else {
+    double* tmp = c->ops64.z;
+    HIP_TRY(unpack<double>(c->stream, src, tmp, c->K, (int)c->rows_per));
+    HIP_TRY(hipMemcpyAsync(u, tmp, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  return STP_OK;
+}
+
+stp_status stp_profile(stp_ctx* c, int enable) {
+  STP_TRY(check_ctx(c));
+  STP_TRY(flush_timing(c));
+  c->profiling = enable != 0;
+  if (enable)
+    for (auto& k : c->kstat) k = stp_kernel_stat{};
+  return STP_OK;
+}
+
+stp_status stp_profile_read(stp_ctx* c, int kernel, stp_kernel_stat* out) {
+  STP_TRY(check_ctx(c));
+  if (kernel < 0 || kernel >= STP_KERNEL_COUNT || !out) {
+    set_error("stp_profile_read: bad kernel id or NULL output");
+    return STP_E_INVALID_ARG;
+  }
+  STP_TRY(flush_timing(c));
+  *out = c->kstat[kernel];
+  return STP_OK;
+}
+
+stp_status stp_get_iterations(const stp_ctx* c, int rhs, int* iterations) {
+  STP_TRY(check_rhs(c, rhs));
+  if (!iterations) {
+    set_error("NULL output");
+    return STP_E_INVALID_ARG;
+  }
+  *iterations = c->iters[rhs];
+  return STP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+stp_status apply_op_t(stp_ctx* c, int op, const double* in_dev, double* out_dev) {
+  Ops<T>& o = ops_of<T>(c);
+  STP_TRY(ensure_ops<T>(c, o));
+  const int K = c->K, J = c->J;
+  const int rows = (int)c->rows_per;
+  T* in_t = (T*)(c->apply_buf + 2 * c->per_rhs);
+  T* out_t = (T*)(c->apply_buf + 3 * c->per_rhs);
+  HIP_TRY(pack<T>(c->stream, in_dev, in_t, K, rows));
+  switch (op) {
+    case STP_OP_W:
+      HIP_TRY(copy<T>(c->stream, in_t, out_t, c->per_rhs));
+      HIP_TRY(wavelet<T>(c->stream, out_t, J, K, 1, true));
+      break;
+    case STP_OP_WT:
+      HIP_TRY(copy<T>(c->stream, in_t, out_t, c->per_rhs));
+      HIP_TRY(wavelet<T>(c->stream, out_t, J, K, 1, false));
+      break;
+    case STP_OP_S:
+      STP_TRY(S_apply<T>(c, o, in_t, out_t, 1));
+      break;
+    case STP_OP_SHAT:
+      STP_TRY(Shat_apply<T>(c, o, in_t, out_t, 1));
+      break;
+    case STP_OP_KX:
+      STP_TRY(KX_apply<T>(c, o, in_t, out_t, 1));
+      break;
+    case STP_OP_KSPACE:
+      STP_TRY(mg_apply<T>(c, o.mg, in_t, out_t, rows, 1.0, nullptr));
+      break;
+    case STP_OP_A:
+      HIP_TRY(apply_A<T>(c->stream, in_t, out_t, K, rows));
+      break;
+    case STP_OP_M:
+      HIP_TRY(apply_M<T>(c->stream, in_t, out_t, K, rows));
+      break;
+    default:
+      set_error("unknown operator");
+      return STP_E_INVALID_ARG;
+  }
+  HIP_TRY(unpack<T>(c->stream, out_t, out_dev, K, rows));
+  return STP_OK;
+}
+
+}  // namespace
+
+extern "C" stp_status stp_apply(stp_ctx* c, int op, int precision, int rhs, const double* in,
+                                double* out, int on_device) {
+  STP_TRY(check_rhs(c, rhs));
+  if (!out || (!in && op != STP_OP_RHS) || (precision != STP_FP64 && precision != STP_MIXED)) {
+    set_error("stp_apply: NULL buffer or bad precision");
+    return STP_E_INVALID_ARG;
+  }
+  if (c->nrhs != 1) {
+    set_error("stp_apply needs a context with nrhs = 1");
+    return STP_E_UNSUPPORTED;
+  }
+  if (op < STP_OP_W || op > STP_OP_M) {
+    set_error("unknown operator");
+    return STP_E_INVALID_ARG;
+  }
+  const int64_t nn = (int64_t)grid_n(c->K) * grid_n(c->K);
+  const int64_t count = nn * c->rows_per;
+  if (!c->apply_buf) {
+    Arena ar;
+    ar.dry = false;
+    ar.list = &c->allocations;
+    STP_TRY(ar.get(&c->apply_buf, 4 * c->per_rhs));
+    c->bytes += ar.bytes;
+  }
+  double* in_dev = on_device ? (double*)in : c->apply_buf;
+  double* out_dev = on_device ? out : c->apply_buf + c->per_rhs;
+  if (op == STP_OP_RHS) {
+    double* f = (double*)(c->apply_buf + 3 * c->per_rhs);
+    STP_TRY(rhs_apply(c, f));
+    HIP_TRY(unpack<double>(c->stream, f, out_dev, c->K, (int)c->rows_per));
+  } else {
+    if (!on_device)
+      HIP_TRY(hipMemcpyAsync(in_dev, in, sizeof(double) * count, hipMemcpyHostToDevice, c->stream));
+    if (precision == STP_FP64)
+      STP_TRY(apply_op_t<double>(c, op, in_dev, out_dev));
+    else
+      STP_TRY(apply_op_t<float>(c, op, in_dev, out_dev));
+  }
+  if (!on_device)
+    HIP_TRY(hipMemcpyAsync(out, out_dev, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return STP_OK;
+}

@@ -1,0 +1,119 @@
+// Host-side launchers of the solver's HIP kernels (gfx950).
+//
+// Every launcher enqueues on `stream`, returns the launch status, and checks
+// nothing about pointer validity: the driver allocates every buffer with the
+// sizes stated next to each launcher and validates sizes before calling.
+// T is the storage and arithmetic type (double, or float for the FP32 inner
+// solve); reductions always accumulate in double.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "layout.h"
+
+namespace stp {
+
+// ---- multigrid for C = a A_x + sigma M_x on level l (Section 3.1, Theorem 3.1,
+// Section 5.1: 3 Gauss-Seidel steps per grid).  Arrays hold `rows` slabs of
+// level l (slab_elems(l) elements each); `sigma` has one value per row (NULL
+// means sigma = 0 for every row).
+
+// Forward smoothing from xin (or from zero when xin == NULL), then the
+// residual restricted to level l-1:  xout <- S_f^3(xin, b),  bc <- P^T (b - C xout).
+// xout must not alias xin.  bc holds `rows` slabs of level l-1.
+template <typename T>
+hipError_t mg_pre(hipStream_t s, const T* xin, const T* b, T* xout, T* bc, int l, int rows,
+                  double a, const double* sigma);
+
+// Coarse correction then backward smoothing: xout <- S_b^3(xin + P ec, b).
+// ec holds `rows` slabs of level l-1; xout must not alias xin.
+template <typename T>
+hipError_t mg_post(hipStream_t s, const T* xin, const T* b, const T* ec, T* xout, int l, int rows,
+                   double a, const double* sigma);
+
+// Exact solve on the one-node grid (level 1): x = b / (4a + sigma/8).
+template <typename T>
+hipError_t mg_coarsest(hipStream_t s, const T* b, T* x, int rows, double a, const double* sigma);
+
+// ---- space-time stencils (Lemma 4.2 and Lemma 4.1, applied row-wise through
+// the Kronecker identity (kron-id) of Section 5.2).  X has nrhs * (2^J+1) slabs
+// of level K; outputs likewise.
+
+// y1 = M (A_t X) + A (L^T X),  y2 = A (M_t X) + M (L X)   (first half of S).
+template <typename T>
+hipError_t time_stencil_pair(hipStream_t s, const T* X, T* y1, T* y2, int J, int K, int nrhs);
+
+// G1 = M (L^T g),  G0 = M (M_t g)   (the data terms of f in Lemma 4.1).
+template <typename T>
+hipError_t rhs_stencil_pair(hipStream_t s, const T* g, T* G1, T* G0, int J, int K, int nrhs);
+
+// out_i = M z1_i + A z2_i, plus M e_b in row 0 of right-hand side b, where
+// e_b = extra + b * extra_stride (one slab); extra == NULL adds nothing.
+template <typename T>
+hipError_t combine(hipStream_t s, const T* z1, const T* z2, const T* extra, int64_t extra_stride,
+                   T* out, int J, int K, int nrhs);
+
+// y = A_x x or y = M_x x on every one of `rows` slabs of level K.
+template <typename T>
+hipError_t apply_A(hipStream_t s, const T* x, T* y, int K, int rows);
+template <typename T>
+hipError_t apply_M(hipStream_t s, const T* x, T* y, int K, int rows);
+
+// ---- three-point wavelet transform along time, in place (Section 3.3).
+template <typename T>
+hipError_t wavelet(hipStream_t s, T* X, int J, int K, int nrhs, bool synthesis);
+
+// ---- vector operations over `nrhs` segments of `n` elements (segment b at
+// offset b * n).  Dots are deterministic: a fixed block decomposition of each
+// segment and a fixed-order second pass, independent of nrhs.
+int dot_blocks(int64_t n);
+template <typename T>
+hipError_t dot(hipStream_t s, const T* a, const T* b, int64_t n, int nrhs, double* partials,
+               double* out);
+
+template <typename T>
+hipError_t copy(hipStream_t s, const T* src, T* dst, int64_t count);
+
+// w += gamma_b p, r -= gamma_b q (per segment b).
+template <typename T>
+hipError_t update_wr(hipStream_t s, T* w, T* r, const T* p, const T* q, const double* gamma,
+                     int64_t n, int nrhs);
+// p = z + beta_b p.
+template <typename T>
+hipError_t update_p(hipStream_t s, T* p, const T* z, const double* beta, int64_t n, int nrhs);
+
+// PCG scalars per right-hand side (all device arrays of length nrhs).
+struct PcgScalars {
+  double* rho;     // r^T z of the current iterate
+  double* rho0;    // r_0^T z_0
+  double* pq;      // p^T q
+  double* rhonew;  // r^T z after the update
+  double* gamma;
+  double* beta;
+  double* target;  // converged once sqrt(r^T z) <= target (0: never, run to maxit)
+  int* active;     // 1 while iterating
+  int* its;        // iterations performed
+  int* status;     // 0 ok/running, 1 converged, -3 breakdown
+};
+// start: rho = rho0 = rhonew, target = tol * sqrt(rho0), its = 0, active unless
+// rho0 == 0 (nothing to solve) or non-finite (breakdown).
+hipError_t pcg_start(hipStream_t s, PcgScalars sc, int nrhs, double tol);
+// gamma = rho / p^T q for active right-hand sides (breakdown if p^T q <= 0).
+hipError_t pcg_gamma(hipStream_t s, PcgScalars sc, int nrhs);
+// beta = rhonew / rho, rho = rhonew, its += 1, convergence test against target.
+hipError_t pcg_beta(hipStream_t s, PcgScalars sc, int nrhs);
+
+// ---- layout conversion and precision casts.
+// Compact FP64 rows of (2^K-1)^2 values <-> slabs of level K in type T.
+template <typename T>
+hipError_t pack(hipStream_t s, const double* src, T* dst, int K, int rows);
+template <typename T>
+hipError_t unpack(hipStream_t s, const T* src, double* dst, int K, int rows);
+template <typename Tin, typename Tout>
+hipError_t cast(hipStream_t s, const Tin* in, Tout* out, int64_t count);
+// r = f - q (FP64);  w += (double) d.
+hipError_t residual64(hipStream_t s, const double* f, const double* q, double* r, int64_t count);
+hipError_t add_correction(hipStream_t s, double* w, const float* d, int64_t count);
+// sigma[b * (N+1) + i] = 2^row_level(i, J)
+hipError_t fill_level_sigma(hipStream_t s, double* sigma, int J, int nrhs);
+
+}  // namespace stp

@@ -1,0 +1,97 @@
+// Internal solver context shared by the C-ABI (api.cpp) and the server (server.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/stp.h"
+#include "kernels.h"
+
+namespace stp {
+
+void set_error(const std::string& msg);
+
+// Multigrid work space for up to `chunk_rows` rows of level K.
+template <typename T>
+struct MgScratch {
+  int K = 0;
+  int64_t chunk_rows = 0;
+  T* xb[kMaxK + 1] = {};   // level l (1..K): smoothed iterate before the coarse correction
+  T* xa[kMaxK + 1] = {};   // level l < K: corrected iterate (the coarse correction of level l+1)
+  T* b[kMaxK + 1] = {};    // level l < K: restricted residual
+};
+
+// Buffers of the operators in type T (one set per precision in use).
+template <typename T>
+struct Ops {
+  bool ready = false;
+  T* X = nullptr;      // nodal W p                                  (vec)
+  T* y = nullptr;      // y1 | y2                                    (2 vec)
+  T* z = nullptr;      // K_x y1 | K_x y2                            (2 vec)
+  MgScratch<T> mg;
+};
+
+template <typename T>
+struct PcgVecs {
+  bool ready = false;
+  T *w = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *rhs = nullptr;
+};
+
+}  // namespace stp
+
+struct stp_ctx {
+  int J = 0, K = 0, nrhs = 1, prec = STP_FP64;
+  stp_options opt{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int64_t slab = 0;        // elements per time row
+  int64_t rows_per = 0;    // 2^J + 1
+  int64_t rows = 0;        // nrhs * rows_per
+  int64_t vec = 0;         // rows * slab (one right-hand side set)
+  int64_t per_rhs = 0;     // rows_per * slab
+  std::vector<void*> allocations;
+  size_t bytes = 0;
+
+  // FP64 data and results
+  double* g = nullptr;      // forcing, nodal (vec)
+  double* u0 = nullptr;     // nrhs slabs
+  double* fhat = nullptr;   // W^T f (vec)
+  double* u = nullptr;      // W w of the last solve (vec)
+  double* w64 = nullptr;    // mixed: FP64 iterate; FP64 mode: alias of pcg64.w
+  double* r64 = nullptr;    // mixed: FP64 outer residual
+  std::vector<int> has_g;
+  bool solved = false;
+  std::vector<int> iters;
+  std::vector<stp_stats> stats;
+
+  double* sigma = nullptr;  // 2^level per time row (K_X)
+  double* partials = nullptr;
+  double* dots = nullptr;   // nrhs
+  stp::PcgScalars sc{};
+  double* target = nullptr;  // nrhs absolute thresholds on sqrt(rho)
+  int* h_active = nullptr;   // pinned host mirror
+  double* h_buf = nullptr;   // pinned host scalars (4 * nrhs)
+
+  // stp_apply staging (allocated on first use): compact in/out and slab in/out
+  double* apply_buf = nullptr;  // 4 * per_rhs doubles
+
+  stp::Ops<double> ops64;
+  stp::Ops<float> ops32;
+  stp::PcgVecs<double> pcg64;
+  stp::PcgVecs<float> pcg32;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  // kernel timing (stp_profile)
+  struct Timed {
+    hipEvent_t a, b;
+    int kernel;
+    double bytes;
+  };
+  bool profiling = false;
+  std::vector<Timed> timed;          // recorded, not yet accumulated
+  std::vector<hipEvent_t> ev_pool;   // reusable events
+  stp_kernel_stat kstat[STP_KERNEL_COUNT] = {};
+};
