@@ -252,16 +252,16 @@ stp_status mg_apply(stp_ctx* c, MgScratch<T>& mg, const T* b, T* x, int64_t rows
       const T* xin = cyc == 0 ? nullptr : xx;
       const double pre_bytes = sizeof(T) * ((xin ? 3.0 : 2.0) * nodes + cnodes);
       STP_TRY(timed_launch(c, STP_KERNEL_MG_PRE, pre_bytes, [&] {
-        return mg_pre<T>(c->stream, xin, bb, mg.xb[K], mg.b[K - 1], K, nr, a, sg);
+        return mg_pre_stream<T>(c->stream, xin, bb, mg.xb[K], mg.b[K - 1], K, nr, a, sg);
       }));
       for (int l = K - 1; l >= 2; --l)
-        HIP_TRY(mg_pre<T>(c->stream, nullptr, mg.b[l], mg.xb[l], mg.b[l - 1], l, nr, a, sg));
+        HIP_TRY(mg_pre_stream<T>(c->stream, nullptr, mg.b[l], mg.xb[l], mg.b[l - 1], l, nr, a, sg));
       HIP_TRY(mg_coarsest<T>(c->stream, mg.b[1], mg.xa[1], nr, a, sg));
       for (int l = 2; l <= K - 1; ++l)
-        HIP_TRY(mg_post<T>(c->stream, mg.xb[l], mg.b[l], mg.xa[l - 1], mg.xa[l], l, nr, a, sg));
+        HIP_TRY(mg_post_stream<T>(c->stream, mg.xb[l], mg.b[l], mg.xa[l - 1], mg.xa[l], l, nr, a, sg));
       const double post_bytes = sizeof(T) * (3.0 * nodes + cnodes);
       STP_TRY(timed_launch(c, STP_KERNEL_MG_POST, post_bytes, [&] {
-        return mg_post<T>(c->stream, mg.xb[K], bb, mg.xa[K - 1], xx, K, nr, a, sg);
+        return mg_post_stream<T>(c->stream, mg.xb[K], bb, mg.xa[K - 1], xx, K, nr, a, sg);
       }));
     }
   }

@@ -30,6 +30,15 @@ template <typename T>
 hipError_t mg_post(hipStream_t s, const T* xin, const T* b, const T* ec, T* xout, int l, int rows,
                    double a, const double* sigma);
 
+// The same two operations by the streaming wavefront kernels (mg_stream.hip),
+// which hold the rows in registers and need no halo along the rows.
+template <typename T>
+hipError_t mg_pre_stream(hipStream_t s, const T* xin, const T* b, T* xout, T* bc, int l, int rows,
+                         double a, const double* sigma);
+template <typename T>
+hipError_t mg_post_stream(hipStream_t s, const T* xin, const T* b, const T* ec, T* xout, int l,
+                          int rows, double a, const double* sigma);
+
 // Exact solve on the one-node grid (level 1): x = b / (4a + sigma/8).
 template <typename T>
 hipError_t mg_coarsest(hipStream_t s, const T* b, T* x, int rows, double a, const double* sigma);
