@@ -229,10 +229,11 @@ stp_status timed_launch(stp_ctx* c, int kernel, double bytes, F f) {
   return STP_OK;
 }
 
-// x = K[a, sigma] b: `vcycles` V-cycles from zero on `rows` slabs of level K.
+// x = K[a, sigma] b: `vcycles` V-cycles from zero on `rows` slabs of level K;
+// with write_Ax, x receives A_x K[a, sigma] b instead.
 template <typename T>
 stp_status mg_apply(stp_ctx* c, MgScratch<T>& mg, const T* b, T* x, int64_t rows, double a,
-                    const double* sigma) {
+                    const double* sigma, bool write_Ax = false) {
   const int K = c->K;
   const int64_t slab = slab_elems(K);
   for (int64_t r0 = 0; r0 < rows; r0 += mg.chunk_rows) {
@@ -241,7 +242,12 @@ stp_status mg_apply(stp_ctx* c, MgScratch<T>& mg, const T* b, T* x, int64_t rows
     T* xx = x + r0 * slab;
     const double* sg = sigma ? sigma + r0 : nullptr;
     if (K == 1) {
-      HIP_TRY(mg_coarsest<T>(c->stream, bb, xx, nr, a, sg));
+      if (write_Ax) {
+        HIP_TRY(mg_coarsest<T>(c->stream, bb, mg.xb[1], nr, a, sg));
+        HIP_TRY(apply_A<T>(c->stream, mg.xb[1], xx, K, nr));
+      } else {
+        HIP_TRY(mg_coarsest<T>(c->stream, bb, xx, nr, a, sg));
+      }
       continue;
     }
     // algorithmic bytes of the fine-level kernels: every input element read
@@ -249,6 +255,8 @@ stp_status mg_apply(stp_ctx* c, MgScratch<T>& mg, const T* b, T* x, int64_t rows
     const double nodes = (double)nr * grid_n(K) * grid_n(K);
     const double cnodes = (double)nr * grid_n(K - 1) * grid_n(K - 1);
     for (int cyc = 0; cyc < c->opt.vcycles; ++cyc) {
+      const bool last = cyc == c->opt.vcycles - 1;
+      // a fused A x output replaces x, so the next cycle could not start from it
       const T* xin = cyc == 0 ? nullptr : xx;
       const double pre_bytes = sizeof(T) * ((xin ? 3.0 : 2.0) * nodes + cnodes);
       STP_TRY(timed_launch(c, STP_KERNEL_MG_PRE, pre_bytes, [&] {
@@ -258,10 +266,12 @@ stp_status mg_apply(stp_ctx* c, MgScratch<T>& mg, const T* b, T* x, int64_t rows
         HIP_TRY(mg_pre_stream<T>(c->stream, nullptr, mg.b[l], mg.xb[l], mg.b[l - 1], l, nr, a, sg));
       HIP_TRY(mg_coarsest<T>(c->stream, mg.b[1], mg.xa[1], nr, a, sg));
       for (int l = 2; l <= K - 1; ++l)
-        HIP_TRY(mg_post_stream<T>(c->stream, mg.xb[l], mg.b[l], mg.xa[l - 1], mg.xa[l], l, nr, a, sg));
+        HIP_TRY(mg_post_stream<T>(c->stream, mg.xb[l], mg.b[l], mg.xa[l - 1], mg.xa[l], l, nr, a, sg,
+                                  false));
       const double post_bytes = sizeof(T) * (3.0 * nodes + cnodes);
       STP_TRY(timed_launch(c, STP_KERNEL_MG_POST, post_bytes, [&] {
-        return mg_post_stream<T>(c->stream, mg.xb[K], bb, mg.xa[K - 1], xx, K, nr, a, sg);
+        return mg_post_stream<T>(c->stream, mg.xb[K], bb, mg.xa[K - 1], xx, K, nr, a, sg,
+                                 write_Ax && last);
       }));
     }
   }
@@ -296,15 +306,13 @@ stp_status Shat_apply(stp_ctx* c, Ops<T>& o, const T* p, T* out, int nrhs) {
 }
 
 // z = K_X r: row i gets K_l A K_l r_i, K_l = MG for (alpha A + 2^l M) (Theorem 3.1).
+// The first application writes A K_l r directly (fused into its last smoothing).
 template <typename T>
 stp_status KX_apply(stp_ctx* c, Ops<T>& o, const T* r, T* z, int nrhs) {
-  const int64_t v = (int64_t)nrhs * c->per_rhs;
   const int64_t rows = (int64_t)nrhs * c->rows_per;
-  T* t1 = o.y;
-  T* t2 = o.y + v;
-  STP_TRY(mg_apply<T>(c, o.mg, r, t1, rows, c->opt.alpha, c->sigma));
-  HIP_TRY(apply_A<T>(c->stream, t1, t2, c->K, (int)rows));
-  STP_TRY(mg_apply<T>(c, o.mg, t2, z, rows, c->opt.alpha, c->sigma));
+  T* t = o.y;
+  STP_TRY(mg_apply<T>(c, o.mg, r, t, rows, c->opt.alpha, c->sigma, true));
+  STP_TRY(mg_apply<T>(c, o.mg, t, z, rows, c->opt.alpha, c->sigma));
   return STP_OK;
 }
 

@@ -35,9 +35,11 @@ hipError_t mg_post(hipStream_t s, const T* xin, const T* b, const T* ec, T* xout
 template <typename T>
 hipError_t mg_pre_stream(hipStream_t s, const T* xin, const T* b, T* xout, T* bc, int l, int rows,
                          double a, const double* sigma);
+// write_Ax: store A_x x (the stiffness applied to the smoothed iterate)
+// instead of x.
 template <typename T>
 hipError_t mg_post_stream(hipStream_t s, const T* xin, const T* b, const T* ec, T* xout, int l,
-                          int rows, double a, const double* sigma);
+                          int rows, double a, const double* sigma, bool write_Ax);
 
 // Exact solve on the one-node grid (level 1): x = b / (4a + sigma/8).
 template <typename T>
