@@ -255,11 +255,6 @@ struct TileShape<float> {
 
 // ------------------------------------------------------------ row stencils
 
-struct Nb {
-  int64_t off;   // offset of the node in the slab
-  bool e, w, nn, s, ne, sw;  // neighbour inside the grid
-};
-
 __device__ inline bool node_of(int64_t idx, int K, int& gx, int& gy) {
   const int pitch = line_pitch(K);
   const int n = grid_n(K);
@@ -288,158 +283,6 @@ __device__ inline T M_at(const T* s, int gx, int gy, int n, int pitch, T m12) {
   return m12 * (T(6) * c + at(s, gx, gy, 1, 0, n, pitch) + at(s, gx, gy, -1, 0, n, pitch) +
                 at(s, gx, gy, 0, 1, n, pitch) + at(s, gx, gy, 0, -1, n, pitch) +
                 at(s, gx, gy, 1, 1, n, pitch) + at(s, gx, gy, -1, -1, n, pitch));
-}
-
-// Temporal combinations at one node of row i from rows i-1, i, i+1 (exact hat
-// integrals, Lemma 4.2): A_t, M_t, L, L^T.
-template <typename T>
-struct TimeCombo {
-  T At, Mt, L, LT;
-};
-template <typename T>
-__device__ inline TimeCombo<T> time_combo(T xm, T x0, T xp, int i, int N, T inv_tau, T tau6) {
-  TimeCombo<T> c;
-  if (i == 0) {
-    c.At = (x0 - xp) * inv_tau;
-    c.Mt = tau6 * (T(2) * x0 + xp);
-    c.L = (xp - x0) / T(2);
-    c.LT = -(x0 + xp) / T(2);
-  } else if (i == N) {
-    c.At = (x0 - xm) * inv_tau;
-    c.Mt = tau6 * (xm + T(2) * x0);
-    c.L = (x0 - xm) / T(2);
-    c.LT = (xm + x0) / T(2);
-  } else {
-    c.At = (T(2) * x0 - xm - xp) * inv_tau;
-    c.Mt = tau6 * ((xm + T(4) * x0) + xp);
-    c.L = (xp - xm) / T(2);
-    c.LT = (xm - xp) / T(2);
-  }
-  return c;
-}
-
-// y1 = M(A_t X) + A(L^T X), y2 = A(M_t X) + M(L X): one thread per slab element.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void time_stencil_pair_kernel(const T* __restrict__ X,
-                                                                   T* __restrict__ y1,
-                                                                   T* __restrict__ y2, int J,
-                                                                   int K) {
-  const int64_t slab = slab_elems(K);
-  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= slab) return;
-  const int N = 1 << J;
-  const int i = blockIdx.y;            // time row within the right-hand side
-  const int rhs = blockIdx.z;
-  const int64_t row = (int64_t)rhs * (N + 1) + i;
-  T* o1 = y1 + row * slab;
-  T* o2 = y2 + row * slab;
-  int gx, gy;
-  if (!node_of(idx, K, gx, gy)) {
-    o1[idx] = T(0);
-    o2[idx] = T(0);
-    return;
-  }
-  const int n = grid_n(K), pitch = line_pitch(K);
-  const T tau = T(1.0 / (double)N);
-  const T inv_tau = T((double)N);
-  const T tau6 = T(1.0 / (6.0 * (double)N));
-  const double h = 1.0 / (double)(1 << K);
-  const T m12 = T(h * h / 12.0);
-  (void)tau;
-  const T* rm = X + (row - (i > 0 ? 1 : 0)) * slab;
-  const T* r0 = X + row * slab;
-  const T* rp = X + (row + (i < N ? 1 : 0)) * slab;
-  // the seven nodes the M stencil touches (A uses the first five)
-  const int dx[7] = {0, 1, -1, 0, 0, 1, -1};
-  const int dy[7] = {0, 0, 0, 1, -1, 1, -1};
-  TimeCombo<T> tc[7];
-#pragma unroll
-  for (int k = 0; k < 7; ++k) {
-    T xm = at(rm, gx, gy, dx[k], dy[k], n, pitch);
-    T x0 = at(r0, gx, gy, dx[k], dy[k], n, pitch);
-    T xp = at(rp, gx, gy, dx[k], dy[k], n, pitch);
-    tc[k] = time_combo(xm, x0, xp, i, N, inv_tau, tau6);
-  }
-  const T MAt = m12 * ((((((T(6) * tc[0].At + tc[1].At) + tc[2].At) + tc[3].At) + tc[4].At) +
-                        tc[5].At) + tc[6].At);
-  const T ALT = (((T(4) * tc[0].LT - tc[1].LT) - tc[2].LT) - tc[3].LT) - tc[4].LT;
-  const T AMt = (((T(4) * tc[0].Mt - tc[1].Mt) - tc[2].Mt) - tc[3].Mt) - tc[4].Mt;
-  const T ML = m12 * ((((((T(6) * tc[0].L + tc[1].L) + tc[2].L) + tc[3].L) + tc[4].L) + tc[5].L) +
-                      tc[6].L);
-  o1[idx] = MAt + ALT;
-  o2[idx] = AMt + ML;
-}
-
-// G1 = M(L^T g), G0 = M(M_t g)
-template <typename T>
-__global__ __launch_bounds__(kBlock) void rhs_stencil_pair_kernel(const T* __restrict__ g,
-                                                                  T* __restrict__ G1,
-                                                                  T* __restrict__ G0, int J,
-                                                                  int K) {
-  const int64_t slab = slab_elems(K);
-  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= slab) return;
-  const int N = 1 << J;
-  const int i = blockIdx.y;
-  const int rhs = blockIdx.z;
-  const int64_t row = (int64_t)rhs * (N + 1) + i;
-  T* o1 = G1 + row * slab;
-  T* o0 = G0 + row * slab;
-  int gx, gy;
-  if (!node_of(idx, K, gx, gy)) {
-    o1[idx] = T(0);
-    o0[idx] = T(0);
-    return;
-  }
-  const int n = grid_n(K), pitch = line_pitch(K);
-  const T inv_tau = T((double)N);
-  const T tau6 = T(1.0 / (6.0 * (double)N));
-  const double h = 1.0 / (double)(1 << K);
-  const T m12 = T(h * h / 12.0);
-  const T* rm = g + (row - (i > 0 ? 1 : 0)) * slab;
-  const T* r0 = g + row * slab;
-  const T* rp = g + (row + (i < N ? 1 : 0)) * slab;
-  const int dx[7] = {0, 1, -1, 0, 0, 1, -1};
-  const int dy[7] = {0, 0, 0, 1, -1, 1, -1};
-  TimeCombo<T> tc[7];
-#pragma unroll
-  for (int k = 0; k < 7; ++k) {
-    T xm = at(rm, gx, gy, dx[k], dy[k], n, pitch);
-    T x0 = at(r0, gx, gy, dx[k], dy[k], n, pitch);
-    T xp = at(rp, gx, gy, dx[k], dy[k], n, pitch);
-    tc[k] = time_combo(xm, x0, xp, i, N, inv_tau, tau6);
-  }
-  o1[idx] = m12 * ((((((T(6) * tc[0].LT + tc[1].LT) + tc[2].LT) + tc[3].LT) + tc[4].LT) +
-                    tc[5].LT) + tc[6].LT);
-  o0[idx] = m12 * ((((((T(6) * tc[0].Mt + tc[1].Mt) + tc[2].Mt) + tc[3].Mt) + tc[4].Mt) +
-                    tc[5].Mt) + tc[6].Mt);
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void combine_kernel(const T* __restrict__ z1,
-                                                         const T* __restrict__ z2,
-                                                         const T* __restrict__ extra,
-                                                         int64_t extra_stride, T* __restrict__ out,
-                                                         int J, int K) {
-  const int64_t slab = slab_elems(K);
-  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= slab) return;
-  const int N = 1 << J;
-  const int i = blockIdx.y;
-  const int rhs = blockIdx.z;
-  const int64_t row = (int64_t)rhs * (N + 1) + i;
-  T* o = out + row * slab;
-  int gx, gy;
-  if (!node_of(idx, K, gx, gy)) {
-    o[idx] = T(0);
-    return;
-  }
-  const int n = grid_n(K), pitch = line_pitch(K);
-  const double h = 1.0 / (double)(1 << K);
-  const T m12 = T(h * h / 12.0);
-  T v = M_at(z1 + row * slab, gx, gy, n, pitch, m12) + A_at(z2 + row * slab, gx, gy, n, pitch);
-  if (i == 0 && extra) v += M_at(extra + (int64_t)rhs * extra_stride, gx, gy, n, pitch, m12);
-  o[idx] = v;
 }
 
 template <typename T, bool IS_A>
@@ -706,10 +549,6 @@ __global__ void fill_level_sigma_kernel(double* sigma, int J, int nrhs) {
   sigma[k] = exp2((double)row_level(i, J));
 }
 
-inline dim3 row_grid(int K, int rows_per_rhs, int nrhs) {
-  return dim3(blocks_for(slab_elems(K)), (unsigned)rows_per_rhs, (unsigned)nrhs);
-}
-
 }  // namespace
 
 // ================================================================ launchers
@@ -739,26 +578,6 @@ hipError_t mg_post(hipStream_t s, const T* xin, const T* b, const T* ec, T* xout
 template <typename T>
 hipError_t mg_coarsest(hipStream_t s, const T* b, T* x, int rows, double a, const double* sigma) {
   mg_coarsest_kernel<T><<<blocks_for(rows), kBlock, 0, s>>>(b, x, rows, a, sigma);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t time_stencil_pair(hipStream_t s, const T* X, T* y1, T* y2, int J, int K, int nrhs) {
-  time_stencil_pair_kernel<T><<<row_grid(K, (1 << J) + 1, nrhs), kBlock, 0, s>>>(X, y1, y2, J, K);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t rhs_stencil_pair(hipStream_t s, const T* g, T* G1, T* G0, int J, int K, int nrhs) {
-  rhs_stencil_pair_kernel<T><<<row_grid(K, (1 << J) + 1, nrhs), kBlock, 0, s>>>(g, G1, G0, J, K);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t combine(hipStream_t s, const T* z1, const T* z2, const T* extra, int64_t extra_stride,
-                   T* out, int J, int K, int nrhs) {
-  combine_kernel<T><<<row_grid(K, (1 << J) + 1, nrhs), kBlock, 0, s>>>(z1, z2, extra, extra_stride,
-                                                                       out, J, K);
   return hipGetLastError();
 }
 
@@ -871,10 +690,6 @@ hipError_t fill_level_sigma(hipStream_t s, double* sigma, int J, int nrhs) {
   template hipError_t mg_post<T>(hipStream_t, const T*, const T*, const T*, T*, int, int, double, \
                                  const double*);                                                 \
   template hipError_t mg_coarsest<T>(hipStream_t, const T*, T*, int, double, const double*);      \
-  template hipError_t time_stencil_pair<T>(hipStream_t, const T*, T*, T*, int, int, int);         \
-  template hipError_t rhs_stencil_pair<T>(hipStream_t, const T*, T*, T*, int, int, int);          \
-  template hipError_t combine<T>(hipStream_t, const T*, const T*, const T*, int64_t, T*, int, int, \
-                                 int);                                                           \
   template hipError_t apply_A<T>(hipStream_t, const T*, T*, int, int);                            \
   template hipError_t apply_M<T>(hipStream_t, const T*, T*, int, int);                            \
   template hipError_t wavelet<T>(hipStream_t, T*, int, int, int, bool);                           \

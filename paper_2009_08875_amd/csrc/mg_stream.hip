@@ -345,7 +345,6 @@ __device__ __forceinline__ void step(State<T>& st, const Args<T>& A, int s0) {
     constexpr int PS = mod(U + 1, kPf);
     if constexpr (!PRE) {
       constexpr bool odd_row = mod(U + 1, 2) == 1;  // s0 is a multiple of 12
-      const int gy = s + 1;
       // coarse row J0 = (s + 1) >> 1 = s0 / 2 + ((U + 1) >> 1); s0 / 2 is even
       constexpr int j0par = ((U + 1) >> 1) & 1;
       if constexpr (odd_row) {
