@@ -28,6 +28,9 @@ WORKLOADS = {
 }
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "PCG unknowns\u00b7iters/s + time-to-solve at 1e-8 rel res; FP32-mixed vs FP64"
+UNIT = "unknowns\u00b7iters/s"
+ROOT = os.path.dirname(os.path.abspath(__file__))
 
 
 def parse():
@@ -84,6 +87,28 @@ def run_solves(stp, ctx, nrhs, tol, steps, warmup, torch, profile=False):
     return (t1 - t0) / steps, stats, kstats
 
 
+def measured_traffic(workload, precision, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the copy-kernel
+    calibration), or None when no summary exists for this workload or the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}_{precision}.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    src = os.path.join(ROOT, "paper_2009_08875_amd", "csrc", rec["source"])
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if digest != rec["sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(seconds_budget):
     """The oracle (NumPy FP64, unmodified) on a bounded sample of the workload:
     PCG on the same mesh (h = 2^-9) with 2^1 + 1 time rows, seeded Fourier
@@ -119,7 +144,7 @@ def cpu_baseline(seconds_budget):
     threads = 1  # NumPy elementwise kernels run on one thread
     return {
         "value": unknowns * its / t1,
-        "unit": "unknowns*iters/s",
+        "unit": UNIT,
         "cores": threads,
         "kind": "oracle",
         "sample": (f"oracle PCG (NumPy FP64) on h=2^-9 with {2 ** J + 1} time rows "
@@ -170,7 +195,8 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": measured_traffic(args.workload, args.precision,
+                                    stp.STP_KERNEL_NAMES[dom]),
         "avg_launch_ms": round(avg_ms, 4),
         "alg_bytes_per_launch": bytes_per_launch,
         "launches": d["launches"],
@@ -201,9 +227,9 @@ def main():
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_sample_seconds)
 
     line = {
-        "metric": "PCG unknowns*iters/s (time-to-solve at 1e-8 rel res; FP32-mixed vs FP64)",
-        "value": unknowns * iters_sum / nrhs * nrhs / t_step if nrhs > 1 else unknowns * its / t_step,
-        "unit": "unknowns*iters/s",
+        "metric": METRIC,
+        "value": (unknowns // nrhs) * iters_sum / t_step,
+        "unit": UNIT,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,

@@ -8,7 +8,7 @@
  *   - trial space: continuous piecewise linears in time (N = 2^J uniform
  *     intervals) times P1 finite elements on the uniform 2^K x 2^K square mesh
  *     cut along its "/" diagonals (Section 4, Section 5.1);
- *   - the Schur-complement system S u = f of eq. (m9), written as in Lemma 4.2
+ *   - the Schur-complement system S u = f of eq. (8), written as in Lemma 4.2
  *     with K_x = two symmetric multigrid V-cycles for A_x (Section 3.1, 5.1);
  *   - PCG on the wavelet-in-time system S-hat w = f-hat, S-hat = W^T S W, with
  *     the block-diagonal preconditioner K_X of Theorem 3.1 (alpha = 0.3), and
@@ -96,7 +96,7 @@ stp_status stp_set_u0(stp_ctx* ctx, int rhs, const double* u0, int on_device);
 stp_status stp_set_g(stp_ctx* ctx, int rhs, const double* g, int on_device);
 
 /* Solve every right-hand side to sqrt(r^T K_X r) <= rel_tol sqrt(f-hat^T K_X f-hat)
- * (r = f-hat - S-hat w, w_0 = 0; the quantity of eq. (stopping)).  rel_tol = 0
+ * (r = f-hat - S-hat w, w_0 = 0; the quantity of eq. (13)).  rel_tol = 0
  * runs exactly maxit iterations.  per_rhs (may be NULL) receives nrhs entries.
  * Returns STP_OK, STP_NOT_CONVERGED (some rhs hit maxit), STP_E_BREAKDOWN. */
 stp_status stp_solve(stp_ctx* ctx, double rel_tol, stp_stats* per_rhs);
@@ -121,7 +121,7 @@ const char* stp_last_error(void);
 #define STP_OP_W       0  /* synthesis W_t (x) Id: wavelet -> nodal (Section 3.3) */
 #define STP_OP_WT      1  /* analysis (W_t (x) Id)^T                              */
 #define STP_OP_S       2  /* S of Lemma 4.2 (nodal)                               */
-#define STP_OP_SHAT    3  /* S-hat = W^T S W (eq. (schur-mat))                    */
+#define STP_OP_SHAT    3  /* S-hat = W^T S W (eq. (11))                    */
 #define STP_OP_KX      4  /* K_X of Theorem 3.1 on wavelet coordinates           */
 #define STP_OP_KSPACE  5  /* K_x (two V-cycles for A_x) on every time row         */
 #define STP_OP_RHS     6  /* f of Lemma 4.1 from the context's g and u0; `in` unused */

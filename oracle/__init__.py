@@ -18,7 +18,7 @@ square with lowest-order elements in space and time:
                       (Section 3.1) and K_j ~ (alpha A_x + 2^j M_x)^{-1}
                       (Theorem 3.1, Section 5.1);
   * ``wavelet``    -- the three-point wavelet transform W_t and its transpose
-                      (Section 3.3, eq. (waveletcomposition));
+                      (Section 3.3, eq. (10));
   * ``schur``      -- S (Lemma 4.2), the right-hand side f (Lemma 4.1),
                       S-hat = W^T S W and f-hat = W^T f (Section 3.4), K_X
                       (Theorem 3.1);

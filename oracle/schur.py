@@ -3,7 +3,7 @@
 Space-time arrays are time-major, shape ``(N + 1, n, n)``: row ``i`` holds the
 spatial coefficients at time node ``t_i``.  A Kronecker product
 ``B_t (x) B_x`` acts by applying ``B_t`` along the time axis and ``B_x`` on
-every row, the matrix-free identity of Section 5.2 (eq. (kron-id)).
+every row, the matrix-free identity of Section 5.2 (eq. (15)).
 """
 from __future__ import annotations
 
@@ -87,7 +87,7 @@ class Problem:
         Z = self.A(Z)
         return multigrid.apply(Z, self.K, a, sigma, self.cycles, self.sweeps)
 
-    # Section 3.4, eq. (schur-mat)
+    # Section 3.4, eq. (11)
     def W(self, w):
         return wavelet.synthesis(w, self.J)
 

@@ -2,7 +2,7 @@
 
 Section 3.3 defines ``W_t`` as the change of basis from the wavelet basis
 Sigma to the single-scale hat basis Phi_t, built level by level
-(eq. (waveletcomposition)); Section 5 uses the three-point wavelets for
+(eq. (10)); Section 5 uses the three-point wavelets for
 continuous piecewise linears.  The coefficients are not printed in the paper;
 the basis used here is:
 

@@ -60,7 +60,7 @@ class stp_kernel_stat(ctypes.Structure):
 
 STP_KERNEL_MG_PRE = 0
 STP_KERNEL_MG_POST = 1
-STP_KERNEL_NAMES = {STP_KERNEL_MG_PRE: "mg_pre_kernel", STP_KERNEL_MG_POST: "mg_post_kernel"}
+STP_KERNEL_NAMES = {STP_KERNEL_MG_PRE: "mg_pre", STP_KERNEL_MG_POST: "mg_post"}
 
 
 class StpError(RuntimeError):

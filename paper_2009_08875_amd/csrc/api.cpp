@@ -294,7 +294,7 @@ stp_status S_apply(stp_ctx* c, Ops<T>& o, const T* X, T* out, int nrhs) {
   return STP_OK;
 }
 
-// out = S-hat p = W^T S W p (eq. (schur-mat)).
+// out = S-hat p = W^T S W p (eq. (11)).
 template <typename T>
 stp_status Shat_apply(stp_ctx* c, Ops<T>& o, const T* p, T* out, int nrhs) {
   const int64_t v = (int64_t)nrhs * c->per_rhs;

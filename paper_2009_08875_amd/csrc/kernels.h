@@ -46,7 +46,7 @@ template <typename T>
 hipError_t mg_coarsest(hipStream_t s, const T* b, T* x, int rows, double a, const double* sigma);
 
 // ---- space-time stencils (Lemma 4.2 and Lemma 4.1, applied row-wise through
-// the Kronecker identity (kron-id) of Section 5.2).  X has nrhs * (2^J+1) slabs
+// the Kronecker identity, eq. (15) of Section 5.2).  X has nrhs * (2^J+1) slabs
 // of level K; outputs likewise.
 
 // y1 = M (A_t X) + A (L^T X),  y2 = A (M_t X) + M (L X)   (first half of S).
