@@ -66,6 +66,8 @@ typedef struct {
   int maxit;         /* PCG iteration limit (inner limit in STP_MIXED); 0 -> 200 */
   double inner_tol;  /* STP_MIXED: relative reduction per inner solve; 0 -> 1e-4 */
   int max_outer;     /* STP_MIXED: refinement-step limit; 0 -> 20 */
+  int graph;         /* replay each PCG iteration from a captured HIP graph:
+                        0 (default) or 1 -> yes (not while profiling), -1 -> no */
 } stp_options;
 
 typedef struct {
@@ -146,6 +148,66 @@ typedef struct {
 } stp_kernel_stat;
 stp_status stp_profile(stp_ctx* ctx, int enable);          /* enabling also clears */
 stp_status stp_profile_read(stp_ctx* ctx, int kernel, stp_kernel_stat* out);
+
+/* ---- serving: continuous batching of independent solves ------------------
+ * Not in the paper (its method solves one problem at a time); this is the
+ * request loop around the same solver.  A server owns a device byte budget,
+ * up to four HIP streams and a worker thread on the device that is current
+ * when it is created.  Requests wait in arrival order; when a slot is free and
+ * the head request's context (stp_footprint) fits in the budget, the worker
+ * admits it together with up to max_batch - 1 waiting requests of the same
+ * (J, K, precision), as the right-hand sides of one batched context (groups of
+ * 1, 2, 4, ... requests).  Running groups advance independently, one PCG
+ * iteration or refinement step at a time, on separate streams, so requests
+ * admitted while others run overlap with them on the device.  Every
+ * right-hand side of a group computes exactly its solo solve (its own
+ * tolerance, scalars and stopping), so results do not depend on the mix.
+ * A finished group writes its solutions and releases its slot at once; its
+ * context is kept for a later group of the same shape and freed when the
+ * budget needs the room.                                                      */
+typedef struct stp_server stp_server;
+
+typedef struct {
+  int J, K;            /* sizes as in stp_create */
+  int precision;       /* STP_FP64 or STP_MIXED */
+  double rel_tol;      /* as in stp_solve */
+  const double* u0;    /* N_x values; NULL -> u0 = 0 */
+  const double* g;     /* (2^J + 1) x N_x nodal values; NULL -> g = 0 */
+  double* u;           /* receives the solution, (2^J + 1) x N_x; NULL -> not kept */
+  int on_device;       /* 1: u0, g and u are device pointers on the server's device */
+} stp_request;
+/* The buffers of a request are read when the request is admitted and u is
+ * written when it finishes; the caller keeps them alive until
+ * stp_server_poll reports the request finished. */
+
+typedef struct {
+  int waiting;                /* requests not yet admitted */
+  int running_groups;         /* groups on the device */
+  int unfinished;             /* submitted and not finished */
+  size_t bytes_in_use;        /* running and cached contexts */
+  size_t peak_bytes;
+  int64_t groups_started;
+  int64_t requests_started;   /* requests_started / groups_started = mean batch */
+} stp_server_stats;
+
+/* opt: solver options for every context (NULL = defaults).  Errors:
+ * STP_E_INVALID_ARG (budget 0, max_slots or max_batch outside [1, 64]). */
+stp_status stp_server_create(size_t hbm_budget_bytes, int max_slots, int max_batch,
+                             const stp_options* opt, stp_server** out);
+/* Queue a request; *id identifies it.  STP_E_OUT_OF_MEMORY when a single
+ * request of this size cannot fit in the budget; STP_E_INVALID_ARG for bad
+ * sizes.  Thread-safe. */
+stp_status stp_server_submit(stp_server* s, const stp_request* req, uint64_t* id);
+/* STP_E_BUSY while the request waits or runs.  Once finished: returns the
+ * request's status (STP_OK, STP_NOT_CONVERGED, STP_E_BREAKDOWN or the error
+ * that stopped it), fills stats and the seconds from submission to completion
+ * (either may be NULL), and forgets the id.  Thread-safe. */
+stp_status stp_server_poll(stp_server* s, uint64_t id, stp_stats* stats, double* latency_seconds);
+/* Block until every submitted request has finished. */
+stp_status stp_server_drain(stp_server* s);
+stp_status stp_server_info(stp_server* s, stp_server_stats* out);
+/* Finish every submitted request, then free the server and its contexts. */
+stp_status stp_server_destroy(stp_server* s);
 
 #ifdef __cplusplus
 }

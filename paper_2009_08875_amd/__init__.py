@@ -34,7 +34,8 @@ STP_OP_W, STP_OP_WT, STP_OP_S, STP_OP_SHAT, STP_OP_KX, STP_OP_KSPACE, STP_OP_RHS
 
 class stp_options(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("vcycles", ctypes.c_int), ("sweeps", ctypes.c_int),
-                ("maxit", ctypes.c_int), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int)]
+                ("maxit", ctypes.c_int), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
+                ("graph", ctypes.c_int)]
 
 
 class stp_stats(ctypes.Structure):
@@ -48,7 +49,18 @@ class stp_stats(ctypes.Structure):
 
 class stp_request(ctypes.Structure):
     _fields_ = [("J", ctypes.c_int), ("K", ctypes.c_int), ("precision", ctypes.c_int),
-                ("rel_tol", ctypes.c_double), ("u0", ctypes.c_void_p), ("g", ctypes.c_void_p)]
+                ("rel_tol", ctypes.c_double), ("u0", ctypes.c_void_p), ("g", ctypes.c_void_p),
+                ("u", ctypes.c_void_p), ("on_device", ctypes.c_int)]
+
+
+class stp_server_stats(ctypes.Structure):
+    _fields_ = [("waiting", ctypes.c_int), ("running_groups", ctypes.c_int),
+                ("unfinished", ctypes.c_int), ("bytes_in_use", ctypes.c_size_t),
+                ("peak_bytes", ctypes.c_size_t), ("groups_started", ctypes.c_int64),
+                ("requests_started", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class stp_kernel_stat(ctypes.Structure):
@@ -95,18 +107,18 @@ def _load():
         "stp_apply": [vp, i, i, i, vp, vp, i],
         "stp_profile": [vp, i],
         "stp_profile_read": [vp, i, ctypes.POINTER(stp_kernel_stat)],
-        "stp_server_create": [sz, i, ctypes.POINTER(stp_options), ctypes.POINTER(vp)],
+        "stp_server_create": [sz, i, i, ctypes.POINTER(stp_options), ctypes.POINTER(vp)],
         "stp_server_submit": [vp, ctypes.POINTER(stp_request), ctypes.POINTER(ctypes.c_uint64)],
-        "stp_server_poll": [vp, ctypes.c_uint64, ctypes.POINTER(i), ctypes.POINTER(stp_stats)],
-        "stp_server_fetch": [vp, ctypes.c_uint64, vp],
+        "stp_server_poll": [vp, ctypes.c_uint64, ctypes.POINTER(stp_stats),
+                            ctypes.POINTER(ctypes.c_double)],
         "stp_server_drain": [vp],
+        "stp_server_info": [vp, ctypes.POINTER(stp_server_stats)],
         "stp_server_destroy": [vp],
     }
     for name, args in sigs.items():
-        if hasattr(lib, name):
-            f = getattr(lib, name)
-            f.argtypes = args
-            f.restype = i
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = i
     lib.stp_destroy.argtypes = [vp]
     lib.stp_destroy.restype = None
     lib.stp_status_string.argtypes = [i]
@@ -242,43 +254,64 @@ def stp_last_error():
 
 # ------------------------------------------------------------ serving C-ABI
 
-def stp_server_create(hbm_budget_bytes, max_slots, options=None):
+# Buffers of submitted requests stay referenced here until the request is
+# collected by stp_server_poll (the library reads and writes them meanwhile).
+_server_refs = {}
+
+
+def stp_server_create(hbm_budget_bytes, max_slots, max_batch=1, options=None):
     h = ctypes.c_void_p()
-    _check(_lib.stp_server_create(hbm_budget_bytes, max_slots, _options(options), ctypes.byref(h)))
+    _check(_lib.stp_server_create(int(hbm_budget_bytes), max_slots, max_batch, _options(options),
+                                  ctypes.byref(h)))
     return h
 
 
-def stp_server_submit(server, J, K, precision, rel_tol, u0=None, g=None):
-    """Submit one solve; ``u0``/``g`` are host float64 arrays (copied at submit)."""
-    if u0 is not None:
-        u0 = np.ascontiguousarray(u0, dtype=np.float64)
-    if g is not None:
-        g = np.ascontiguousarray(g, dtype=np.float64)
-    req = stp_request(J, K, precision, rel_tol,
-                      u0.ctypes.data if u0 is not None else None,
-                      g.ctypes.data if g is not None else None)
+def stp_server_submit(server, J, K, precision, rel_tol, u0=None, g=None, u=None):
+    """Queue one solve.  u0 (N_x), g ((2^J+1) N_x) and u (output, same size as
+    g) are float64 host arrays or CUDA tensors (all on the same side); None
+    means zero data / no output."""
+    n = grid_n(K) ** 2
+    bufs = [(u0, n), (g, ((1 << J) + 1) * n), (u, ((1 << J) + 1) * n)]
+    ptrs, sides = [], set()
+    for a, count in bufs:
+        p, dev = _ptr(a, count)
+        ptrs.append(p)
+        if a is not None:
+            sides.add(dev)
+    if len(sides) > 1:
+        raise TypeError("u0, g and u must all be host arrays or all be device tensors")
+    req = stp_request(J, K, precision, rel_tol, ptrs[0], ptrs[1], ptrs[2], sides.pop() if sides else 0)
     rid = ctypes.c_uint64()
     _check(_lib.stp_server_submit(server, ctypes.byref(req), ctypes.byref(rid)))
+    _server_refs[(server.value, rid.value)] = (u0, g, u)
     return rid.value
 
 
 def stp_server_poll(server, rid):
-    done = ctypes.c_int()
+    """None while the request waits or runs; then (status, stats, latency_s).
+    A failed request raises StpError."""
     st = stp_stats()
-    _check(_lib.stp_server_poll(server, rid, ctypes.byref(done), ctypes.byref(st)))
-    return bool(done.value), st.as_dict()
-
-
-def stp_server_fetch(server, rid, out):
-    p, dev = _ptr(out)
-    if dev:
-        raise TypeError("stp_server_fetch writes host memory")
-    return _check(_lib.stp_server_fetch(server, rid, p))
+    lat = ctypes.c_double()
+    status = _lib.stp_server_poll(server, rid, ctypes.byref(st), ctypes.byref(lat))
+    if status == STP_E_BUSY:
+        return None
+    _server_refs.pop((server.value, rid), None)
+    _check(status)
+    return status, st.as_dict(), lat.value
 
 
 def stp_server_drain(server):
     return _check(_lib.stp_server_drain(server))
 
 
+def stp_server_info(server):
+    out = stp_server_stats()
+    _check(_lib.stp_server_info(server, ctypes.byref(out)))
+    return out.as_dict()
+
+
 def stp_server_destroy(server):
-    return _check(_lib.stp_server_destroy(server))
+    status = _check(_lib.stp_server_destroy(server))
+    for key in [k for k in _server_refs if k[0] == server.value]:
+        del _server_refs[key]
+    return status

@@ -26,21 +26,6 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 
 }  // namespace stp
 
-#define HIP_TRY(expr)                                                                       \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess) {                                                                 \
-      set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                         \
-      return STP_E_DEVICE;                                                                  \
-    }                                                                                       \
-  } while (0)
-
-#define STP_TRY(expr)                       \
-  do {                                      \
-    stp_status s_ = (expr);                 \
-    if (s_ < 0) return s_;                  \
-  } while (0)
-
 namespace {
 
 stp_options resolve(const stp_options* o) {
@@ -52,6 +37,7 @@ stp_options resolve(const stp_options* o) {
   if (r.maxit <= 0) r.maxit = 200;
   if (r.inner_tol <= 0.0) r.inner_tol = 1e-4;
   if (r.max_outer <= 0) r.max_outer = 20;
+  if (r.graph > 0) r.graph = 1;
   return r;
 }
 
@@ -132,7 +118,7 @@ stp_status plan_context(Arena& ar, stp_ctx* c) {
   STP_TRY(ar.get(&c->u, vec));
   STP_TRY(ar.get(&c->sigma, c->rows));
   STP_TRY(ar.get(&c->partials, (int64_t)c->nrhs * 1024));
-  STP_TRY(ar.get(&c->dots, c->nrhs));
+  STP_TRY(ar.get(&c->tolv, c->nrhs));
   STP_TRY(ar.get(&c->sc.rho, c->nrhs));
   STP_TRY(ar.get(&c->sc.rho0, c->nrhs));
   STP_TRY(ar.get(&c->sc.pq, c->nrhs));
@@ -147,6 +133,12 @@ stp_status plan_context(Arena& ar, stp_ctx* c) {
   if (c->prec == STP_FP64) {
     STP_TRY(plan_pcg(ar, c->pcg64, vec, false));
   } else {
+    STP_TRY(ar.get(&c->ms.rho0_first, c->nrhs));
+    STP_TRY(ar.get(&c->ms.rel, c->nrhs));
+    STP_TRY(ar.get(&c->ms.done, c->nrhs));
+    STP_TRY(ar.get(&c->ms.status, c->nrhs));
+    STP_TRY(ar.get(&c->ms.outer, c->nrhs));
+    STP_TRY(ar.get(&c->ms.inner_its, c->nrhs));
     STP_TRY(ar.get(&c->w64, vec));
     STP_TRY(ar.get(&c->r64, vec));
     STP_TRY(plan_ops(ar, c->ops32, c->K, c->rows, vec));
@@ -165,8 +157,12 @@ void free_all(stp_ctx* c) {
   c->ev_pool.clear();
   for (void* p : c->allocations) (void)hipFree(p);
   c->allocations.clear();
-  if (c->h_active) (void)hipHostFree(c->h_active);
-  if (c->h_buf) (void)hipHostFree(c->h_buf);
+  if (c->graph64.exec) (void)hipGraphExecDestroy(c->graph64.exec);
+  if (c->graph32.exec) (void)hipGraphExecDestroy(c->graph32.exec);
+  if (c->h_flags) (void)hipHostFree(c->h_flags);
+  if (c->h_stats) (void)hipHostFree(c->h_stats);
+  if (c->h_tol) (void)hipHostFree(c->h_tol);
+  if (c->ev_flags) (void)hipEventDestroy(c->ev_flags);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -338,167 +334,247 @@ stp_status rhs_apply(stp_ctx* c, double* f) {
 }
 
 // ------------------------------------------------------------ PCG
+//
+// A solve is a sequence of units of device work.  After each unit the host
+// reads the per-right-hand-side flags (active, done) through pinned memory
+// and picks the next unit; every decision that needs a PCG scalar is taken on
+// the device (pcg_start, pcg_gamma, pcg_beta, mixed_adjust), so a unit never
+// waits for the host.  stp_solve runs the units back to back; the server
+// interleaves the units of many contexts.
 
-stp_status read_active(stp_ctx* c, bool& any) {
-  HIP_TRY(hipMemcpyAsync(c->h_active, c->sc.active, sizeof(int) * c->nrhs, hipMemcpyDeviceToHost,
-                         c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  any = false;
-  for (int b = 0; b < c->nrhs; ++b) any = any || c->h_active[b];
+// PCG start on S-hat w = rhs, w_0 = 0 (Section 3.4): r = rhs, z = K_X r,
+// rho0 = r^T z, p = z.
+template <typename T>
+stp_status pcg_init(stp_ctx* c, PcgVecs<T>& v, const T* rhs, const double* tol) {
+  Ops<T>& o = ops_of<T>(c);
+  HIP_TRY(hipMemsetAsync(v.w, 0, sizeof(T) * c->vec, c->stream));
+  HIP_TRY(copy<T>(c->stream, rhs, v.r, c->vec));
+  STP_TRY(KX_apply<T>(c, o, v.r, v.z, c->nrhs));
+  HIP_TRY(dot<T>(c->stream, v.r, v.z, c->per_rhs, c->nrhs, c->partials, c->sc.rhonew));
+  HIP_TRY(pcg_start(c->stream, c->sc, c->nrhs, tol));
+  HIP_TRY(copy<T>(c->stream, v.z, v.p, c->vec));
   return STP_OK;
 }
 
-// PCG on S-hat w = rhs (w_0 = 0) in type T (Section 3.4).  If `adjust` is
-// set, it is called after the start (rho0 known) to rewrite targets/active.
-template <typename T, typename Adjust>
-stp_status pcg_run(stp_ctx* c, PcgVecs<T>& v, const T* rhs, double tol, int maxit, Adjust adjust) {
+// One PCG iteration for every right-hand side; inactive ones get gamma = 0
+// and keep w and r.  No host synchronisation, no memset: graph-capturable.
+template <typename T>
+stp_status pcg_iteration(stp_ctx* c, PcgVecs<T>& v) {
   Ops<T>& o = ops_of<T>(c);
   const int nrhs = c->nrhs;
   const int64_t n = c->per_rhs;
-  const int64_t vec = c->vec;
-  HIP_TRY(hipMemsetAsync(v.w, 0, sizeof(T) * vec, c->stream));
-  HIP_TRY(copy<T>(c->stream, rhs, v.r, vec));
+  STP_TRY(Shat_apply<T>(c, o, v.p, v.q, nrhs));
+  HIP_TRY(dot<T>(c->stream, v.p, v.q, n, nrhs, c->partials, c->sc.pq));
+  HIP_TRY(pcg_gamma(c->stream, c->sc, nrhs));
+  HIP_TRY(update_wr<T>(c->stream, v.w, v.r, v.p, v.q, c->sc.gamma, n, nrhs));
   STP_TRY(KX_apply<T>(c, o, v.r, v.z, nrhs));
   HIP_TRY(dot<T>(c->stream, v.r, v.z, n, nrhs, c->partials, c->sc.rhonew));
-  HIP_TRY(pcg_start(c->stream, c->sc, nrhs, tol));
-  STP_TRY(adjust());
-  HIP_TRY(copy<T>(c->stream, v.z, v.p, vec));
-  for (int it = 0; it < maxit; ++it) {
-    bool any = false;
-    STP_TRY(read_active(c, any));
-    if (!any) break;
-    STP_TRY(Shat_apply<T>(c, o, v.p, v.q, nrhs));
-    HIP_TRY(dot<T>(c->stream, v.p, v.q, n, nrhs, c->partials, c->sc.pq));
-    HIP_TRY(pcg_gamma(c->stream, c->sc, nrhs));
-    HIP_TRY(update_wr<T>(c->stream, v.w, v.r, v.p, v.q, c->sc.gamma, n, nrhs));
-    STP_TRY(KX_apply<T>(c, o, v.r, v.z, nrhs));
-    HIP_TRY(dot<T>(c->stream, v.r, v.z, n, nrhs, c->partials, c->sc.rhonew));
-    HIP_TRY(pcg_beta(c->stream, c->sc, nrhs));
-    HIP_TRY(update_p<T>(c->stream, v.p, v.z, c->sc.beta, n, nrhs));
-  }
+  HIP_TRY(pcg_beta(c->stream, c->sc, nrhs, c->opt.maxit));
+  HIP_TRY(update_p<T>(c->stream, v.p, v.z, c->sc.beta, n, nrhs));
   return STP_OK;
 }
 
-struct HostScalars {
-  std::vector<double> rho, rho0;
-  std::vector<int> its, status, active;
-};
+template <typename T>
+stp_ctx::Graph& graph_of(stp_ctx* c);
+template <>
+stp_ctx::Graph& graph_of<double>(stp_ctx* c) { return c->graph64; }
+template <>
+stp_ctx::Graph& graph_of<float>(stp_ctx* c) { return c->graph32; }
 
-stp_status read_scalars(stp_ctx* c, HostScalars& h) {
-  const int nr = c->nrhs;
-  h.rho.resize(nr);
-  h.rho0.resize(nr);
-  h.its.resize(nr);
-  h.status.resize(nr);
-  h.active.resize(nr);
-  HIP_TRY(hipMemcpyAsync(h.rho.data(), c->sc.rho, sizeof(double) * nr, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipMemcpyAsync(h.rho0.data(), c->sc.rho0, sizeof(double) * nr, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipMemcpyAsync(h.its.data(), c->sc.its, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipMemcpyAsync(h.status.data(), c->sc.status, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipMemcpyAsync(h.active.data(), c->sc.active, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  return STP_OK;
-}
-
-stp_status solve_fp64(stp_ctx* c, double tol) {
-  PcgVecs<double>& v = c->pcg64;
-  STP_TRY(pcg_run<double>(c, v, c->fhat, tol, c->opt.maxit, [] { return (stp_status)STP_OK; }));
-  HostScalars h;
-  STP_TRY(read_scalars(c, h));
-  for (int b = 0; b < c->nrhs; ++b) {
-    stp_stats& s = c->stats[b];
-    s.iterations = h.its[b];
-    s.outer_iterations = 0;
-    s.rel_residual = h.rho0[b] > 0 ? std::sqrt(std::max(h.rho[b], 0.0) / h.rho0[b]) : 0.0;
-    s.status = h.status[b] == -3 ? STP_E_BREAKDOWN
-               : (h.status[b] == 1 || (tol > 0 && s.rel_residual <= tol) || h.rho0[b] == 0.0)
-                   ? STP_OK
-                   : STP_NOT_CONVERGED;
-    if (tol == 0.0 && h.status[b] != -3) s.status = STP_OK;
-  }
-  HIP_TRY(copy<double>(c->stream, v.w, c->u, c->vec));
-  return STP_OK;
-}
-
-// FP32 inner PCG with FP64 outer residual and refinement (spec form (1)).
-stp_status solve_mixed(stp_ctx* c, double tol) {
-  const int nr = c->nrhs;
-  PcgVecs<float>& v = c->pcg32;
-  const int64_t vec = c->vec;
-  std::vector<double> rho0_first(nr, -1.0), last_rel(nr, 1.0);
-  std::vector<int> done(nr, 0), inner_its(nr, 0), outer(nr, 0), status(nr, STP_NOT_CONVERGED);
-  HIP_TRY(hipMemsetAsync(c->w64, 0, sizeof(double) * vec, c->stream));
-  HIP_TRY(copy<double>(c->stream, c->fhat, c->r64, vec));
-  std::vector<double> tgt(nr);
-  std::vector<int> act(nr);
-  for (int k = 0; k < c->opt.max_outer; ++k) {
-    if (k > 0) {
-      STP_TRY(Shat_apply<double>(c, c->ops64, c->w64, c->r64, nr));
-      HIP_TRY(residual64(c->stream, c->fhat, c->r64, c->r64, vec));
+// One iteration, replayed from a captured HIP graph once one exists.  The
+// first iteration of a context runs eagerly (it also initialises the
+// kernels' launch-shape caches); the second is captured.  Profiling needs
+// per-launch events and always runs eagerly.
+template <typename T>
+stp_status iterate(stp_ctx* c, PcgVecs<T>& v) {
+  stp_ctx::Graph& g = graph_of<T>(c);
+  if (!c->use_graph || c->profiling || c->stream == nullptr) return pcg_iteration<T>(c, v);
+  if (!g.exec) {
+    if (!g.warm) {
+      g.warm = true;
+      return pcg_iteration<T>(c, v);
     }
-    HIP_TRY((cast<double, float>(c->stream, c->r64, v.rhs, vec)));
-    auto adjust = [&]() -> stp_status {
-      HostScalars h;
-      STP_TRY(read_scalars(c, h));
-      for (int b = 0; b < nr; ++b) {
-        if (done[b]) {
-          act[b] = 0;
-          tgt[b] = 0;
-          continue;
-        }
-        outer[b] = k;
-        if (k == 0) rho0_first[b] = h.rho0[b];
-        const double rel = rho0_first[b] > 0 ? std::sqrt(std::max(h.rho0[b], 0.0) / rho0_first[b]) : 0.0;
-        last_rel[b] = rel;
-        if (h.status[b] == -3) {
-          done[b] = 1;
-          status[b] = STP_E_BREAKDOWN;
-          act[b] = 0;
-        } else if (rho0_first[b] <= 0.0 || (tol > 0 && rel <= tol) || h.rho0[b] == 0.0) {
-          done[b] = 1;
-          status[b] = STP_OK;
-          act[b] = 0;
-        } else {
-          act[b] = 1;
-        }
-        // stop the inner solve at a relative reduction of inner_tol, but not
-        // below what the outer tolerance still needs
-        const double s0 = std::sqrt(std::max(h.rho0[b], 0.0));
-        const double floor_abs = 0.5 * tol * std::sqrt(std::max(rho0_first[b], 0.0));
-        tgt[b] = std::max(c->opt.inner_tol * s0, floor_abs);
-      }
-      HIP_TRY(hipMemcpyAsync(c->sc.target, tgt.data(), sizeof(double) * nr, hipMemcpyHostToDevice, c->stream));
-      HIP_TRY(hipMemcpyAsync(c->sc.active, act.data(), sizeof(int) * nr, hipMemcpyHostToDevice, c->stream));
-      HIP_TRY(hipStreamSynchronize(c->stream));
-      return STP_OK;
-    };
-    STP_TRY(pcg_run<float>(c, v, v.rhs, 0.0, c->opt.maxit, adjust));
-    HostScalars h;
-    STP_TRY(read_scalars(c, h));
-    bool all_done = true;
-    for (int b = 0; b < nr; ++b) {
-      if (!done[b]) {
-        inner_its[b] += h.its[b];
-        if (h.status[b] == -3) {
-          done[b] = 1;
-          status[b] = STP_E_BREAKDOWN;
-        }
-      }
-      all_done = all_done && done[b];
+    HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    const stp_status st = pcg_iteration<T>(c, v);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+    if (st < 0) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
     }
-    if (all_done) break;
-    HIP_TRY(add_correction(c->stream, c->w64, v.w, vec));
+    HIP_TRY(e);
+    const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIP_TRY(ei);
   }
+  HIP_TRY(hipGraphLaunch(g.exec, c->stream));
+  return STP_OK;
+}
+
+// Copy the lane flags to pinned host memory and mark the end of the unit.
+stp_status post_flags(stp_ctx* c) {
+  const int nr = c->nrhs;
+  HIP_TRY(hipMemcpyAsync(c->h_flags, c->sc.active, sizeof(int) * nr, hipMemcpyDeviceToHost,
+                         c->stream));
+  if (c->prec == STP_MIXED)
+    HIP_TRY(hipMemcpyAsync(c->h_flags + nr, c->ms.done, sizeof(int) * nr, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIP_TRY(hipEventRecord(c->ev_flags, c->stream));
+  return STP_OK;
+}
+
+bool any_active(const stp_ctx* c) {
+  for (int b = 0; b < c->nrhs; ++b)
+    if (c->h_flags[b]) return true;
+  return false;
+}
+
+// Last unit: u = W w, and the statistics to pinned host memory.
+stp_status finish_unit(stp_ctx* c) {
+  const int nr = c->nrhs;
+  double* hs = c->h_stats;
+  int* hi = (int*)(c->h_stats + 2 * nr);
+  if (c->prec == STP_FP64) {
+    HIP_TRY(copy<double>(c->stream, c->pcg64.w, c->u, c->vec));
+    HIP_TRY(hipMemcpyAsync(hs, c->sc.rho, sizeof(double) * nr, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(hs + nr, c->sc.rho0, sizeof(double) * nr, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(hi, c->sc.its, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(hi + nr, c->sc.status, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
+  } else {
+    HIP_TRY(copy<double>(c->stream, c->w64, c->u, c->vec));
+    HIP_TRY(hipMemcpyAsync(hs, c->ms.rel, sizeof(double) * nr, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(hi, c->ms.inner_its, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(hi + nr, c->ms.status, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(hi + 2 * nr, c->ms.outer, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(hi + 3 * nr, c->ms.done, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIP_TRY(wavelet<double>(c->stream, c->u, c->J, c->K, nr, true));
+  HIP_TRY(hipEventRecord(c->ev1, c->stream));
+  HIP_TRY(hipEventRecord(c->ev_flags, c->stream));
+  c->drv.phase = stp_ctx::kFinish;
+  return STP_OK;
+}
+
+// Statistics of a finished solve from the pinned copies.
+void collect_stats(stp_ctx* c) {
+  const int nr = c->nrhs;
+  const double* hs = c->h_stats;
+  const int* hi = (const int*)(c->h_stats + 2 * nr);
+  float ms = 0.0f;
+  if (hipEventElapsedTime(&ms, c->ev0, c->ev1) != hipSuccess) ms = 0.0f;
   for (int b = 0; b < nr; ++b) {
     stp_stats& s = c->stats[b];
-    s.iterations = inner_its[b];
-    s.outer_iterations = outer[b] + 1;
-    s.rel_residual = last_rel[b];
-    s.status = done[b] ? status[b] : STP_NOT_CONVERGED;
+    const double tol = c->h_tol[b];
+    if (c->prec == STP_FP64) {
+      const double rho = hs[b], rho0 = hs[nr + b];
+      const int st = hi[nr + b];
+      s.iterations = hi[b];
+      s.outer_iterations = 0;
+      s.rel_residual = rho0 > 0 ? std::sqrt(std::max(rho, 0.0) / rho0) : 0.0;
+      if (st == -3)
+        s.status = STP_E_BREAKDOWN;
+      else if (st == 1 || (tol > 0 && s.rel_residual <= tol) || rho0 == 0.0 || tol == 0.0)
+        s.status = STP_OK;
+      else
+        s.status = STP_NOT_CONVERGED;
+    } else {
+      s.iterations = hi[b];
+      s.rel_residual = hs[b];
+      s.outer_iterations = hi[2 * nr + b] + 1;
+      const int st = hi[nr + b], done = hi[3 * nr + b];
+      s.status = !done ? STP_NOT_CONVERGED : st == -3 ? STP_E_BREAKDOWN : STP_OK;
+    }
+    s.seconds = ms * 1e-3;
+    c->iters[b] = s.iterations;
   }
-  HIP_TRY(copy<double>(c->stream, c->w64, c->u, vec));
+  c->drv.phase = stp_ctx::kDone;
+}
+
+// Mixed form: outer step k > 0 starts from the FP64 residual f-hat - S-hat w.
+stp_status mixed_outer_start(stp_ctx* c, int k) {
+  PcgVecs<float>& v = c->pcg32;
+  if (k > 0) {
+    STP_TRY(Shat_apply<double>(c, c->ops64, c->w64, c->r64, c->nrhs));
+    HIP_TRY(residual64(c->stream, c->fhat, c->r64, c->r64, c->vec));
+  }
+  HIP_TRY((cast<double, float>(c->stream, c->r64, v.rhs, c->vec)));
+  STP_TRY(pcg_init<float>(c, v, v.rhs, nullptr));
+  HIP_TRY(mixed_adjust(c->stream, c->sc, c->ms, c->nrhs, c->tolv, c->opt.inner_tol, k));
   return STP_OK;
 }
+
+}  // namespace
+
+namespace stp {
+
+// First unit of a solve: f (Lemma 4.1), f-hat = W^T f, the PCG start.
+// `tol` holds one relative tolerance per right-hand side (host memory).
+stp_status drive_begin(stp_ctx* c, const double* tol) {
+  const int nr = c->nrhs;
+  for (int b = 0; b < nr; ++b) c->h_tol[b] = tol[b];
+  c->solved = false;
+  HIP_TRY(hipEventRecord(c->ev0, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->tolv, c->h_tol, sizeof(double) * nr, hipMemcpyHostToDevice, c->stream));
+  STP_TRY(rhs_apply(c, c->fhat));
+  HIP_TRY(wavelet<double>(c->stream, c->fhat, c->J, c->K, nr, false));
+  if (c->prec == STP_FP64) {
+    STP_TRY(pcg_init<double>(c, c->pcg64, c->fhat, c->tolv));
+  } else {
+    HIP_TRY(mixed_reset(c->stream, c->ms, nr));
+    HIP_TRY(hipMemsetAsync(c->w64, 0, sizeof(double) * c->vec, c->stream));
+    HIP_TRY(copy<double>(c->stream, c->fhat, c->r64, c->vec));
+    STP_TRY(mixed_outer_start(c, 0));
+  }
+  c->drv.phase = stp_ctx::kIter;
+  c->drv.outer_k = 0;
+  c->drv.adjusted = true;
+  STP_TRY(post_flags(c));
+  return STP_OK;
+}
+
+// Whether the last unit has completed (never blocks).
+bool drive_ready(stp_ctx* c) { return hipEventQuery(c->ev_flags) == hipSuccess; }
+
+stp_status drive_wait(stp_ctx* c) {
+  HIP_TRY(hipEventSynchronize(c->ev_flags));
+  return STP_OK;
+}
+
+// Enqueue the unit that follows the completed one; phase becomes kDone when
+// the solve has finished and its statistics are in c->stats.
+stp_status drive_next(stp_ctx* c) {
+  stp_ctx::Drive& d = c->drv;
+  if (d.phase == stp_ctx::kFinish) {
+    collect_stats(c);
+    c->solved = true;
+    return STP_OK;
+  }
+  if (d.phase != stp_ctx::kIter) {
+    set_error("no solve in progress");
+    return STP_E_INVALID_ARG;
+  }
+  if (any_active(c)) {
+    if (c->prec == STP_FP64)
+      STP_TRY(iterate<double>(c, c->pcg64));
+    else
+      STP_TRY(iterate<float>(c, c->pcg32));
+    d.adjusted = false;
+    return post_flags(c);
+  }
+  if (c->prec == STP_FP64 || d.adjusted) return finish_unit(c);
+  // mixed: the inner solve has ended; refine w and start the next outer step
+  HIP_TRY(mixed_inner_done(c->stream, c->sc, c->ms, c->nrhs));
+  HIP_TRY(add_correction(c->stream, c->w64, c->pcg32.w, c->per_rhs, c->nrhs, c->ms.status));
+  if (d.outer_k + 1 >= c->opt.max_outer) return finish_unit(c);
+  d.outer_k += 1;
+  STP_TRY(mixed_outer_start(c, d.outer_k));
+  d.adjusted = true;
+  return post_flags(c);
+}
+
+}  // namespace stp
+
+namespace {
 
 template <typename T>
 stp_status ensure_ops(stp_ctx* c, Ops<T>& o) {
@@ -614,6 +690,7 @@ stp_status stp_create(int J, int K, int nrhs, int precision, const stp_options* 
   }
   init_dims(c, J, K, nrhs, precision);
   c->opt = o;
+  c->use_graph = o.graph >= 0;
   c->has_g.assign(nrhs, 0);
   c->iters.assign(nrhs, 0);
   c->stats.assign(nrhs, stp_stats{});
@@ -641,8 +718,10 @@ stp_status stp_create(int J, int K, int nrhs, int precision, const stp_options* 
   stp_status st = plan_context(ar, c);
   if (st < 0) return fail(st);
   c->bytes = ar.bytes;
-  if (hipHostMalloc((void**)&c->h_active, sizeof(int) * nrhs) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_buf, sizeof(double) * 4 * nrhs) != hipSuccess ||
+  if (hipHostMalloc((void**)&c->h_flags, sizeof(int) * 2 * nrhs) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_stats, sizeof(double) * 4 * nrhs) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_tol, sizeof(double) * nrhs) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_flags, hipEventDisableTiming) != hipSuccess ||
       hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
     set_error("pinned host allocation or event creation failed");
     return fail(STP_E_DEVICE);
@@ -674,7 +753,6 @@ stp_status stp_set_u0(stp_ctx* c, int rhs, const double* u0, int on_device) {
   double* tmp = c->ops64.z;  // compact staging area (large enough: >= vec elements)
   STP_TRY(stage_in(c, u0, on_device, nn, tmp));
   HIP_TRY(pack<double>(c->stream, tmp, dst, c->K, 1));
-  HIP_TRY(hipStreamSynchronize(c->stream));
   return STP_OK;
 }
 
@@ -690,7 +768,6 @@ stp_status stp_set_g(stp_ctx* c, int rhs, const double* g, int on_device) {
   double* tmp = c->ops64.z;
   STP_TRY(stage_in(c, g, on_device, nn * c->rows_per, tmp));
   HIP_TRY(pack<double>(c->stream, tmp, dst, c->K, (int)c->rows_per));
-  HIP_TRY(hipStreamSynchronize(c->stream));
   c->has_g[rhs] = 1;
   return STP_OK;
 }
@@ -701,27 +778,30 @@ stp_status stp_solve(stp_ctx* c, double rel_tol, stp_stats* per_rhs) {
     set_error("rel_tol must be in [0, 1)");
     return STP_E_INVALID_ARG;
   }
-  HIP_TRY(hipEventRecord(c->ev0, c->stream));
-  STP_TRY(rhs_apply(c, c->fhat));
-  HIP_TRY(wavelet<double>(c->stream, c->fhat, c->J, c->K, c->nrhs, false));
-  if (c->prec == STP_FP64)
-    STP_TRY(solve_fp64(c, rel_tol));
-  else
-    STP_TRY(solve_mixed(c, rel_tol));
-  HIP_TRY(wavelet<double>(c->stream, c->u, c->J, c->K, c->nrhs, true));
-  HIP_TRY(hipEventRecord(c->ev1, c->stream));
-  HIP_TRY(hipEventSynchronize(c->ev1));
-  float ms = 0.0f;
-  HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  if (c->drv.phase == stp_ctx::kIter || c->drv.phase == stp_ctx::kFinish) {
+    set_error("a solve is already in progress on this context");
+    return STP_E_INVALID_ARG;
+  }
+  std::vector<double> tol(c->nrhs, rel_tol);
+  auto run = [&]() -> stp_status {
+    STP_TRY(drive_begin(c, tol.data()));
+    while (c->drv.phase != stp_ctx::kDone) {
+      STP_TRY(drive_wait(c));
+      STP_TRY(drive_next(c));
+    }
+    return STP_OK;
+  };
+  const stp_status st = run();
+  if (st < 0) {
+    c->drv.phase = stp_ctx::kIdle;
+    return st;
+  }
   stp_status worst = STP_OK;
   for (int b = 0; b < c->nrhs; ++b) {
-    c->stats[b].seconds = ms * 1e-3;
-    c->iters[b] = c->stats[b].iterations;
     if (c->stats[b].status == STP_E_BREAKDOWN) worst = STP_E_BREAKDOWN;
     else if (c->stats[b].status == STP_NOT_CONVERGED && worst == STP_OK) worst = STP_NOT_CONVERGED;
     if (per_rhs) per_rhs[b] = c->stats[b];
   }
-  c->solved = true;
   if (worst == STP_E_BREAKDOWN) set_error("PCG breakdown (p^T S-hat p <= 0 or non-finite)");
   return worst;
 }

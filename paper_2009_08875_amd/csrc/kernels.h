@@ -19,24 +19,14 @@ namespace stp {
 
 // Forward smoothing from xin (or from zero when xin == NULL), then the
 // residual restricted to level l-1:  xout <- S_f^3(xin, b),  bc <- P^T (b - C xout).
-// xout must not alias xin.  bc holds `rows` slabs of level l-1.
-template <typename T>
-hipError_t mg_pre(hipStream_t s, const T* xin, const T* b, T* xout, T* bc, int l, int rows,
-                  double a, const double* sigma);
-
-// Coarse correction then backward smoothing: xout <- S_b^3(xin + P ec, b).
-// ec holds `rows` slabs of level l-1; xout must not alias xin.
-template <typename T>
-hipError_t mg_post(hipStream_t s, const T* xin, const T* b, const T* ec, T* xout, int l, int rows,
-                   double a, const double* sigma);
-
-// The same two operations by the streaming wavefront kernels (mg_stream.hip),
-// which hold the rows in registers and need no halo along the rows.
+// xout must not alias xin; bc holds `rows` slabs of level l-1.  Streaming
+// wavefront kernels (mg_stream.hip): rows held in registers, no halo along rows.
 template <typename T>
 hipError_t mg_pre_stream(hipStream_t s, const T* xin, const T* b, T* xout, T* bc, int l, int rows,
                          double a, const double* sigma);
-// write_Ax: store A_x x (the stiffness applied to the smoothed iterate)
-// instead of x.
+// Coarse correction then backward smoothing: xout <- S_b^3(xin + P ec, b);
+// ec holds `rows` slabs of level l-1.  write_Ax: store A_x x (the stiffness
+// applied to the smoothed iterate) instead of x.
 template <typename T>
 hipError_t mg_post_stream(hipStream_t s, const T* xin, const T* b, const T* ec, T* xout, int l,
                           int rows, double a, const double* sigma, bool write_Ax);
@@ -105,13 +95,32 @@ struct PcgScalars {
   int* its;        // iterations performed
   int* status;     // 0 ok/running, 1 converged, -3 breakdown
 };
-// start: rho = rho0 = rhonew, target = tol * sqrt(rho0), its = 0, active unless
-// rho0 == 0 (nothing to solve) or non-finite (breakdown).
-hipError_t pcg_start(hipStream_t s, PcgScalars sc, int nrhs, double tol);
+// start: rho = rho0 = rhonew, target = tol_b * sqrt(rho0) (tol: device array of
+// nrhs relative tolerances, or NULL for 0 = run to maxit), its = 0, active
+// unless rho0 == 0 (nothing to solve) or non-finite (breakdown).
+hipError_t pcg_start(hipStream_t s, PcgScalars sc, int nrhs, const double* tol);
 // gamma = rho / p^T q for active right-hand sides (breakdown if p^T q <= 0).
 hipError_t pcg_gamma(hipStream_t s, PcgScalars sc, int nrhs);
-// beta = rhonew / rho, rho = rhonew, its += 1, convergence test against target.
-hipError_t pcg_beta(hipStream_t s, PcgScalars sc, int nrhs);
+// beta = rhonew / rho, rho = rhonew, its += 1, convergence test against target;
+// a right-hand side that reaches maxit iterations stops (status stays 0).
+hipError_t pcg_beta(hipStream_t s, PcgScalars sc, int nrhs, int maxit);
+
+// State of the FP32-inner / FP64-outer form per right-hand side (device arrays).
+struct MixedState {
+  double* rho0_first;  // r^T K_X r of the first outer step
+  double* rel;         // sqrt(rho0 / rho0_first) at the latest outer step
+  int* done;           // 1 once converged or broken down
+  int* status;         // 0 converged, -3 breakdown, 1 still running
+  int* outer;          // index of the latest outer step
+  int* inner_its;      // inner iterations, summed
+};
+hipError_t mixed_reset(hipStream_t s, MixedState ms, int nrhs);
+// after the inner PCG start of outer step k: convergence test of the FP64
+// residual against tol_b, inner target max(inner_tol sqrt(rho0), tol_b/2 sqrt(rho0_first))
+hipError_t mixed_adjust(hipStream_t s, PcgScalars sc, MixedState ms, int nrhs, const double* tol,
+                        double inner_tol, int k);
+// after an inner solve: inner_its += its, breakdown marks the right-hand side done
+hipError_t mixed_inner_done(hipStream_t s, PcgScalars sc, MixedState ms, int nrhs);
 
 // ---- layout conversion and precision casts.
 // Compact FP64 rows of (2^K-1)^2 values <-> slabs of level K in type T.
@@ -121,9 +130,11 @@ template <typename T>
 hipError_t unpack(hipStream_t s, const T* src, double* dst, int K, int rows);
 template <typename Tin, typename Tout>
 hipError_t cast(hipStream_t s, const Tin* in, Tout* out, int64_t count);
-// r = f - q (FP64);  w += (double) d.
+// r = f - q (FP64).
 hipError_t residual64(hipStream_t s, const double* f, const double* q, double* r, int64_t count);
-hipError_t add_correction(hipStream_t s, double* w, const float* d, int64_t count);
+// w += (double) d per segment of n elements, except segments with status[b] == -3.
+hipError_t add_correction(hipStream_t s, double* w, const float* d, int64_t n, int nrhs,
+                          const int* status);
 // sigma[b * (N+1) + i] = 2^row_level(i, J)
 hipError_t fill_level_sigma(hipStream_t s, double* sigma, int J, int nrhs);
 

@@ -2,8 +2,8 @@
 //
 // All operators are constant-coefficient stencils on uniform grids, so no
 // matrix is stored: every kernel reads its input once per needed element and
-// recomputes coefficients from the mesh width.  The hot kernels are the fused
-// multigrid smoothing kernels; see mg_pre_kernel for their tiling scheme.
+// recomputes coefficients from the mesh width.  The hot kernels (multigrid smoothing and
+// the space-time stencils) live in mg_stream.hip and stencil.hip.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -20,217 +20,9 @@ inline unsigned blocks_for(int64_t count, int per_block = kBlock) {
   return (unsigned)((count + per_block - 1) / per_block);
 }
 
-// Stencil coefficients of C = a A_x + sigma M_x on mesh width h = 2^-l:
-// centre 4a + sigma h^2/2, axis neighbours -a + sigma h^2/12, and the two
-// neighbours across the "/" diagonal sigma h^2/12.
-struct Coef {
-  double c0, c1, c2;
-};
-__device__ inline Coef coefficients(double a, double sigma, int l) {
-  double h = 1.0 / (double)(1 << l);
-  double m = h * h / 12.0;
-  return {4.0 * a + 6.0 * m * sigma, -a + m * sigma, m * sigma};
-}
-
 // ---------------------------------------------------------------- multigrid
-//
-// A workgroup owns a TW x TH tile of one slab and stages it in LDS together
-// with a halo of H nodes.  The three-colour Gauss-Seidel phases run in LDS;
-// phase p (0-based) updates only the region whose distance to the LDS border
-// is at least p + 1, so after 3 steps x 3 colours the values are exact (equal
-// to a global sweep) at distance >= 9 from the border.  The pre-smoothing
-// kernel additionally needs the residual one node further out and the
-// restriction one more, hence H = 11 there and H = 9 in the post-smoothing
-// kernel.  Overlapping halos are recomputed redundantly by neighbouring tiles;
-// every tile computes the same value for a node (same operands, same order),
-// so the result does not depend on the tiling.
 
-constexpr int kSweeps = 3;
-constexpr int kHpre = 3 * kSweeps + 2;
-constexpr int kHpost = 3 * kSweeps;
-
-template <typename T, int W, int HH>
-__device__ inline void relax_colour(T (*xs)[W], const T (*bs)[W], int c, int lo, int hix, int hiy,
-                                    int gx0, int gy0, int n, T c0inv, T c1, T c2) {
-  const int r = threadIdx.x & 31;
-  const int q = threadIdx.x >> 5;
-  for (int ly = lo + q; ly <= hiy; ly += kBlock / 32) {
-    const int gy = gy0 + ly;
-    if (gy < 1 || gy > n) continue;
-    const int first = lo + (((c - gy - gx0 - lo) % 3) + 3) % 3;
-    for (int lx = first + 3 * r; lx <= hix; lx += 96) {
-      const int gx = gx0 + lx;
-      if (gx < 1 || gx > n) continue;
-      T off = c1 * (((xs[ly][lx + 1] + xs[ly][lx - 1]) + xs[ly + 1][lx]) + xs[ly - 1][lx]) +
-              c2 * (xs[ly + 1][lx + 1] + xs[ly - 1][lx - 1]);
-      xs[ly][lx] = (bs[ly][lx] - off) * c0inv;
-    }
-  }
-}
-
-template <typename T, int TW, int TH>
-__global__ __launch_bounds__(kBlock) void mg_pre_kernel(const T* __restrict__ xin,
-                                                        const T* __restrict__ b,
-                                                        T* __restrict__ xout, T* __restrict__ bc,
-                                                        int l, int tiles_x, double a,
-                                                        const double* __restrict__ sigma) {
-  constexpr int H = kHpre;
-  constexpr int W = TW + 2 * H;
-  constexpr int HH = TH + 2 * H;
-  __shared__ T xs[HH][W];
-  __shared__ T bs[HH][W];
-
-  const int row = blockIdx.y;
-  const int tx = blockIdx.x % tiles_x;
-  const int ty = blockIdx.x / tiles_x;
-  const int n = grid_n(l);
-  const int pitch = line_pitch(l);
-  const int64_t slab = slab_elems(l);
-  const int nc = grid_n(l - 1);
-  const int pitch_c = line_pitch(l - 1);
-  const int64_t slab_c = slab_elems(l - 1);
-  const int gx0 = 1 + tx * TW - H;  // node coordinates of LDS cell (0, 0)
-  const int gy0 = 1 + ty * TH - H;
-
-  const T* xr = xin ? xin + (int64_t)row * slab : nullptr;
-  const T* br = b + (int64_t)row * slab;
-  for (int idx = threadIdx.x; idx < W * HH; idx += kBlock) {
-    const int ly = idx / W, lx = idx - (idx / W) * W;
-    const int gx = gx0 + lx, gy = gy0 + ly;
-    const bool in = gx >= 1 && gx <= n && gy >= 1 && gy <= n;
-    const int64_t off = (int64_t)(gy - 1) * pitch + (gx - 1);
-    xs[ly][lx] = (in && xr) ? xr[off] : T(0);
-    bs[ly][lx] = in ? br[off] : T(0);
-  }
-  __syncthreads();
-
-  const Coef cf = coefficients(a, sigma ? sigma[row] : 0.0, l);
-  const T c0 = (T)cf.c0, c0inv = (T)(1.0 / cf.c0), c1 = (T)cf.c1, c2 = (T)cf.c2;
-
-  for (int sw = 0; sw < kSweeps; ++sw) {
-    for (int c = 0; c < 3; ++c) {
-      const int p = sw * 3 + c;
-      relax_colour<T, W, HH>(xs, bs, c, p + 1, W - 2 - p, HH - 2 - p, gx0, gy0, n, c0inv, c1, c2);
-      __syncthreads();
-    }
-  }
-
-  // residual r = b - C x, in place of b, on the nodes the restriction reads
-  for (int idx = threadIdx.x; idx < (TW + 2) * (TH + 2); idx += kBlock) {
-    const int ly = H - 1 + idx / (TW + 2);
-    const int lx = H - 1 + idx % (TW + 2);
-    const int gx = gx0 + lx, gy = gy0 + ly;
-    T r = T(0);
-    if (gx >= 1 && gx <= n && gy >= 1 && gy <= n) {
-      T off = c1 * (((xs[ly][lx + 1] + xs[ly][lx - 1]) + xs[ly + 1][lx]) + xs[ly - 1][lx]) +
-              c2 * (xs[ly + 1][lx + 1] + xs[ly - 1][lx - 1]);
-      r = bs[ly][lx] - (c0 * xs[ly][lx] + off);
-    }
-    bs[ly][lx] = r;
-  }
-
-  // smoothed x of the tile interior
-  T* xo = xout + (int64_t)row * slab;
-  for (int idx = threadIdx.x; idx < TW * TH; idx += kBlock) {
-    const int ly = H + idx / TW, lx = H + idx % TW;
-    const int gx = gx0 + lx, gy = gy0 + ly;
-    if (gx <= n && gy <= n) xo[(int64_t)(gy - 1) * pitch + (gx - 1)] = xs[ly][lx];
-  }
-  __syncthreads();
-
-  // restriction: coarse node (I, J) sits at fine node (2I, 2J) and collects its
-  // residual plus half of each of the six neighbours' residuals
-  T* bco = bc + (int64_t)row * slab_c;
-  for (int idx = threadIdx.x; idx < (TW / 2) * (TH / 2); idx += kBlock) {
-    const int I = 1 + tx * (TW / 2) + idx % (TW / 2);
-    const int J = 1 + ty * (TH / 2) + idx / (TW / 2);
-    if (I > nc || J > nc) continue;
-    const int lx = 2 * I - gx0, ly = 2 * J - gy0;
-    T half = ((((bs[ly][lx + 1] + bs[ly][lx - 1]) + bs[ly + 1][lx]) + bs[ly - 1][lx]) +
-              bs[ly + 1][lx + 1]) +
-             bs[ly - 1][lx - 1];
-    bco[(int64_t)(J - 1) * pitch_c + (I - 1)] = bs[ly][lx] + T(0.5) * half;
-  }
-}
-
-template <typename T>
-__device__ inline T coarse_at(const T* ec, int I, int J, int nc, int pitch_c) {
-  return (I >= 1 && I <= nc && J >= 1 && J <= nc) ? ec[(int64_t)(J - 1) * pitch_c + (I - 1)] : T(0);
-}
-
-template <typename T, int TW, int TH>
-__global__ __launch_bounds__(kBlock) void mg_post_kernel(const T* __restrict__ xin,
-                                                         const T* __restrict__ b,
-                                                         const T* __restrict__ ec,
-                                                         T* __restrict__ xout, int l, int tiles_x,
-                                                         double a,
-                                                         const double* __restrict__ sigma) {
-  constexpr int H = kHpost;
-  constexpr int W = TW + 2 * H;
-  constexpr int HH = TH + 2 * H;
-  __shared__ T xs[HH][W];
-  __shared__ T bs[HH][W];
-
-  const int row = blockIdx.y;
-  const int tx = blockIdx.x % tiles_x;
-  const int ty = blockIdx.x / tiles_x;
-  const int n = grid_n(l);
-  const int pitch = line_pitch(l);
-  const int64_t slab = slab_elems(l);
-  const int nc = grid_n(l - 1);
-  const int pitch_c = line_pitch(l - 1);
-  const int64_t slab_c = slab_elems(l - 1);
-  const int gx0 = 1 + tx * TW - H;
-  const int gy0 = 1 + ty * TH - H;
-
-  const T* xr = xin + (int64_t)row * slab;
-  const T* br = b + (int64_t)row * slab;
-  const T* er = ec + (int64_t)row * slab_c;
-  for (int idx = threadIdx.x; idx < W * HH; idx += kBlock) {
-    const int ly = idx / W, lx = idx - (idx / W) * W;
-    const int gx = gx0 + lx, gy = gy0 + ly;
-    T xv = T(0), bv = T(0);
-    if (gx >= 1 && gx <= n && gy >= 1 && gy <= n) {
-      const int64_t off = (int64_t)(gy - 1) * pitch + (gx - 1);
-      bv = br[off];
-      // x + P e: P1 interpolation of the coarse correction on the "/" mesh
-      const int I = gx >> 1, J = gy >> 1;
-      T e;
-      if (!(gx & 1) && !(gy & 1)) {
-        e = coarse_at(er, I, J, nc, pitch_c);
-      } else if ((gx & 1) && !(gy & 1)) {
-        e = T(0.5) * (coarse_at(er, I, J, nc, pitch_c) + coarse_at(er, I + 1, J, nc, pitch_c));
-      } else if (!(gx & 1) && (gy & 1)) {
-        e = T(0.5) * (coarse_at(er, I, J, nc, pitch_c) + coarse_at(er, I, J + 1, nc, pitch_c));
-      } else {
-        e = T(0.5) * (coarse_at(er, I, J, nc, pitch_c) + coarse_at(er, I + 1, J + 1, nc, pitch_c));
-      }
-      xv = xr[off] + e;
-    }
-    xs[ly][lx] = xv;
-    bs[ly][lx] = bv;
-  }
-  __syncthreads();
-
-  const Coef cf = coefficients(a, sigma ? sigma[row] : 0.0, l);
-  const T c0inv = (T)(1.0 / cf.c0), c1 = (T)cf.c1, c2 = (T)cf.c2;
-  for (int sw = 0; sw < kSweeps; ++sw) {
-    for (int cc = 0; cc < 3; ++cc) {
-      const int p = sw * 3 + cc;
-      relax_colour<T, W, HH>(xs, bs, 2 - cc, p + 1, W - 2 - p, HH - 2 - p, gx0, gy0, n, c0inv, c1,
-                             c2);
-      __syncthreads();
-    }
-  }
-
-  T* xo = xout + (int64_t)row * slab;
-  for (int idx = threadIdx.x; idx < TW * TH; idx += kBlock) {
-    const int ly = H + idx / TW, lx = H + idx % TW;
-    const int gx = gx0 + lx, gy = gy0 + ly;
-    if (gx <= n && gy <= n) xo[(int64_t)(gy - 1) * pitch + (gx - 1)] = xs[ly][lx];
-  }
-}
-
+// Exact solve on the one-node grid (level 1, h = 1/2).
 template <typename T>
 __global__ void mg_coarsest_kernel(const T* __restrict__ b, T* __restrict__ x, int rows, double a,
                                    const double* __restrict__ sigma) {
@@ -241,17 +33,6 @@ __global__ void mg_coarsest_kernel(const T* __restrict__ b, T* __restrict__ x, i
   const int64_t slab = slab_elems(1);
   x[(int64_t)row * slab] = (T)((double)b[(int64_t)row * slab] / c0);
 }
-
-template <typename T>
-struct TileShape;
-template <>
-struct TileShape<double> {
-  static constexpr int TW = 32, TH = 32;
-};
-template <>
-struct TileShape<float> {
-  static constexpr int TW = 32, TH = 32;
-};
 
 // ------------------------------------------------------------ row stencils
 
@@ -429,16 +210,17 @@ __global__ __launch_bounds__(kBlock) void update_p_kernel(T* __restrict__ p,
   p[k] = (T)((double)z[k] + bt * (double)p[k]);
 }
 
-__global__ void pcg_start_kernel(PcgScalars sc, int nrhs, double tol) {
+__global__ void pcg_start_kernel(PcgScalars sc, int nrhs, const double* __restrict__ tol) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nrhs) return;
   const double rho = sc.rhonew[b];
+  const double t = tol ? tol[b] : 0.0;
   sc.rho[b] = rho;
   sc.rho0[b] = rho;
   sc.its[b] = 0;
   sc.gamma[b] = 0.0;
   sc.beta[b] = 0.0;
-  sc.target[b] = tol > 0.0 ? tol * sqrt(rho) : 0.0;
+  sc.target[b] = t > 0.0 ? t * sqrt(rho) : 0.0;
   if (!isfinite(rho) || rho < 0.0) {
     sc.active[b] = 0;
     sc.status[b] = -3;
@@ -468,7 +250,7 @@ __global__ void pcg_gamma_kernel(PcgScalars sc, int nrhs) {
   sc.gamma[b] = sc.rho[b] / pq;
 }
 
-__global__ void pcg_beta_kernel(PcgScalars sc, int nrhs) {
+__global__ void pcg_beta_kernel(PcgScalars sc, int nrhs, int maxit) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nrhs) return;
   if (!sc.active[b]) {
@@ -488,7 +270,66 @@ __global__ void pcg_beta_kernel(PcgScalars sc, int nrhs) {
   if (rn == 0.0 || sqrt(rn) <= sc.target[b]) {
     sc.active[b] = 0;
     sc.status[b] = 1;
+  } else if (sc.its[b] >= maxit) {
+    sc.active[b] = 0;  // iteration limit: status stays 0 (not converged)
   }
+}
+
+// Mixed form, start of outer step k (after the inner PCG start): decide per
+// right-hand side whether the FP64 residual already meets the tolerance, and
+// set the inner stopping target.
+__global__ void mixed_adjust_kernel(PcgScalars sc, MixedState ms, int nrhs,
+                                    const double* __restrict__ tol, double inner_tol, int k) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nrhs) return;
+  if (ms.done[b]) {
+    sc.active[b] = 0;
+    sc.target[b] = 0.0;
+    return;
+  }
+  const double t = tol[b];
+  const double rho0 = sc.rho0[b];
+  ms.outer[b] = k;
+  if (k == 0) ms.rho0_first[b] = rho0;
+  const double first = ms.rho0_first[b];
+  const double rel = first > 0.0 ? sqrt(fmax(rho0, 0.0) / first) : 0.0;
+  ms.rel[b] = rel;
+  if (sc.status[b] == -3) {
+    ms.done[b] = 1;
+    ms.status[b] = -3;
+    sc.active[b] = 0;
+  } else if (first <= 0.0 || (t > 0.0 && rel <= t) || rho0 == 0.0) {
+    ms.done[b] = 1;
+    ms.status[b] = 0;
+    sc.active[b] = 0;
+  } else {
+    sc.active[b] = 1;
+  }
+  // stop the inner solve at a relative reduction of inner_tol, but not below
+  // what the outer tolerance still needs
+  sc.target[b] = fmax(inner_tol * sqrt(fmax(rho0, 0.0)), 0.5 * t * sqrt(fmax(first, 0.0)));
+}
+
+// Mixed form, end of an inner solve: count its iterations, record breakdown.
+__global__ void mixed_inner_done_kernel(PcgScalars sc, MixedState ms, int nrhs) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nrhs || ms.done[b]) return;
+  ms.inner_its[b] += sc.its[b];
+  if (sc.status[b] == -3) {
+    ms.done[b] = 1;
+    ms.status[b] = -3;
+  }
+}
+
+__global__ void mixed_reset_kernel(MixedState ms, int nrhs) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nrhs) return;
+  ms.rho0_first[b] = -1.0;
+  ms.rel[b] = 1.0;
+  ms.done[b] = 0;
+  ms.status[b] = 1;
+  ms.outer[b] = 0;
+  ms.inner_its[b] = 0;
 }
 
 // ------------------------------------------------------------ layout / casts
@@ -534,11 +375,16 @@ __global__ __launch_bounds__(kBlock) void residual64_kernel(const double* __rest
   if (i < count) r[i] = f[i] - q[i];
 }
 
+// w += (double) d per right-hand side segment, except where status is -3
+// (the inner solve broke down: its correction is not finite).
 __global__ __launch_bounds__(kBlock) void add_correction_kernel(double* __restrict__ w,
                                                                 const float* __restrict__ d,
-                                                                int64_t count) {
+                                                                int64_t n,
+                                                                const int* __restrict__ status) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < count) w[i] += (double)d[i];
+  if (i >= n || status[blockIdx.y] == -3) return;
+  const int64_t k = (int64_t)blockIdx.y * n + i;
+  w[k] += (double)d[k];
 }
 
 __global__ void fill_level_sigma_kernel(double* sigma, int J, int nrhs) {
@@ -552,28 +398,6 @@ __global__ void fill_level_sigma_kernel(double* sigma, int J, int nrhs) {
 }  // namespace
 
 // ================================================================ launchers
-
-template <typename T>
-hipError_t mg_pre(hipStream_t s, const T* xin, const T* b, T* xout, T* bc, int l, int rows,
-                  double a, const double* sigma) {
-  constexpr int TW = TileShape<T>::TW, TH = TileShape<T>::TH;
-  const int n = grid_n(l);
-  const int tiles_x = (n + TW - 1) / TW, tiles_y = (n + TH - 1) / TH;
-  mg_pre_kernel<T, TW, TH><<<dim3(tiles_x * tiles_y, rows), kBlock, 0, s>>>(xin, b, xout, bc, l,
-                                                                            tiles_x, a, sigma);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t mg_post(hipStream_t s, const T* xin, const T* b, const T* ec, T* xout, int l, int rows,
-                   double a, const double* sigma) {
-  constexpr int TW = TileShape<T>::TW, TH = TileShape<T>::TH;
-  const int n = grid_n(l);
-  const int tiles_x = (n + TW - 1) / TW, tiles_y = (n + TH - 1) / TH;
-  mg_post_kernel<T, TW, TH><<<dim3(tiles_x * tiles_y, rows), kBlock, 0, s>>>(xin, b, ec, xout, l,
-                                                                             tiles_x, a, sigma);
-  return hipGetLastError();
-}
 
 template <typename T>
 hipError_t mg_coarsest(hipStream_t s, const T* b, T* x, int rows, double a, const double* sigma) {
@@ -635,7 +459,7 @@ hipError_t update_p(hipStream_t s, T* p, const T* z, const double* beta, int64_t
   return hipGetLastError();
 }
 
-hipError_t pcg_start(hipStream_t s, PcgScalars sc, int nrhs, double tol) {
+hipError_t pcg_start(hipStream_t s, PcgScalars sc, int nrhs, const double* tol) {
   pcg_start_kernel<<<blocks_for(nrhs, 64), 64, 0, s>>>(sc, nrhs, tol);
   return hipGetLastError();
 }
@@ -643,8 +467,8 @@ hipError_t pcg_gamma(hipStream_t s, PcgScalars sc, int nrhs) {
   pcg_gamma_kernel<<<blocks_for(nrhs, 64), 64, 0, s>>>(sc, nrhs);
   return hipGetLastError();
 }
-hipError_t pcg_beta(hipStream_t s, PcgScalars sc, int nrhs) {
-  pcg_beta_kernel<<<blocks_for(nrhs, 64), 64, 0, s>>>(sc, nrhs);
+hipError_t pcg_beta(hipStream_t s, PcgScalars sc, int nrhs, int maxit) {
+  pcg_beta_kernel<<<blocks_for(nrhs, 64), 64, 0, s>>>(sc, nrhs, maxit);
   return hipGetLastError();
 }
 
@@ -672,8 +496,23 @@ hipError_t residual64(hipStream_t s, const double* f, const double* q, double* r
   return hipGetLastError();
 }
 
-hipError_t add_correction(hipStream_t s, double* w, const float* d, int64_t count) {
-  add_correction_kernel<<<blocks_for(count), kBlock, 0, s>>>(w, d, count);
+hipError_t add_correction(hipStream_t s, double* w, const float* d, int64_t n, int nrhs,
+                          const int* status) {
+  add_correction_kernel<<<dim3(blocks_for(n), nrhs), kBlock, 0, s>>>(w, d, n, status);
+  return hipGetLastError();
+}
+
+hipError_t mixed_reset(hipStream_t s, MixedState ms, int nrhs) {
+  mixed_reset_kernel<<<blocks_for(nrhs, 64), 64, 0, s>>>(ms, nrhs);
+  return hipGetLastError();
+}
+hipError_t mixed_adjust(hipStream_t s, PcgScalars sc, MixedState ms, int nrhs, const double* tol,
+                        double inner_tol, int k) {
+  mixed_adjust_kernel<<<blocks_for(nrhs, 64), 64, 0, s>>>(sc, ms, nrhs, tol, inner_tol, k);
+  return hipGetLastError();
+}
+hipError_t mixed_inner_done(hipStream_t s, PcgScalars sc, MixedState ms, int nrhs) {
+  mixed_inner_done_kernel<<<blocks_for(nrhs, 64), 64, 0, s>>>(sc, ms, nrhs);
   return hipGetLastError();
 }
 
@@ -685,10 +524,6 @@ hipError_t fill_level_sigma(hipStream_t s, double* sigma, int J, int nrhs) {
 
 // ---------------------------------------------------------- instantiations
 #define STP_INSTANTIATE(T)                                                                        \
-  template hipError_t mg_pre<T>(hipStream_t, const T*, const T*, T*, T*, int, int, double,       \
-                                const double*);                                                  \
-  template hipError_t mg_post<T>(hipStream_t, const T*, const T*, const T*, T*, int, int, double, \
-                                 const double*);                                                 \
   template hipError_t mg_coarsest<T>(hipStream_t, const T*, T*, int, double, const double*);      \
   template hipError_t apply_A<T>(hipStream_t, const T*, T*, int, int);                            \
   template hipError_t apply_M<T>(hipStream_t, const T*, T*, int, int);                            \

@@ -13,6 +13,21 @@ namespace stp {
 
 void set_error(const std::string& msg);
 
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      stp::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+      return STP_E_DEVICE;                                                                  \
+    }                                                                                       \
+  } while (0)
+
+#define STP_TRY(expr)                       \
+  do {                                      \
+    stp_status s_ = (expr);                 \
+    if (s_ < 0) return s_;                  \
+  } while (0)
+
 // Multigrid work space for up to `chunk_rows` rows of level K.
 template <typename T>
 struct MgScratch {
@@ -69,11 +84,31 @@ struct stp_ctx {
 
   double* sigma = nullptr;  // 2^level per time row (K_X)
   double* partials = nullptr;
-  double* dots = nullptr;   // nrhs
   stp::PcgScalars sc{};
-  double* target = nullptr;  // nrhs absolute thresholds on sqrt(rho)
-  int* h_active = nullptr;   // pinned host mirror
-  double* h_buf = nullptr;   // pinned host scalars (4 * nrhs)
+  stp::MixedState ms{};      // STP_MIXED only
+  double* tolv = nullptr;    // relative tolerance per right-hand side (device)
+
+  // pinned host memory read between units of a solve
+  int* h_flags = nullptr;     // active[nrhs] | done[nrhs]
+  double* h_stats = nullptr;  // 2 * nrhs doubles, then 4 * nrhs ints
+  double* h_tol = nullptr;    // nrhs
+  hipEvent_t ev_flags = nullptr;
+
+  // solve driver state (see drive_begin / drive_next)
+  enum Phase { kIdle = 0, kIter, kFinish, kDone };
+  struct Drive {
+    int phase = kIdle;
+    int outer_k = 0;
+    bool adjusted = false;  // the last unit ended with an inner PCG start
+  } drv;
+
+  // captured PCG iteration per precision
+  struct Graph {
+    bool warm = false;
+    hipGraphExec_t exec = nullptr;
+  };
+  bool use_graph = false;
+  Graph graph64, graph32;
 
   // stp_apply staging (allocated on first use): compact in/out and slab in/out
   double* apply_buf = nullptr;  // 4 * per_rhs doubles
@@ -95,3 +130,16 @@ struct stp_ctx {
   std::vector<hipEvent_t> ev_pool;   // reusable events
   stp_kernel_stat kstat[STP_KERNEL_COUNT] = {};
 };
+
+namespace stp {
+// Solve driver (api.cpp): a solve is a chain of device-side units; the host
+// picks the next unit from pinned per-right-hand-side flags once the last one
+// has completed.  drive_begin enqueues the first unit (tol: nrhs relative
+// tolerances in host memory); drive_ready polls without blocking; drive_next
+// enqueues the next unit, and sets drv.phase = kDone (statistics in
+// ctx->stats, solution in ctx->u) after the last one.
+stp_status drive_begin(stp_ctx* c, const double* tol);
+bool drive_ready(stp_ctx* c);
+stp_status drive_wait(stp_ctx* c);
+stp_status drive_next(stp_ctx* c);
+}  // namespace stp

@@ -60,3 +60,20 @@ def test_status_strings(stp):
 def test_null_context_is_rejected(stp):
     assert stp._lib.stp_solve(None, 1e-8, None) == stp.STP_E_INVALID_ARG
     assert "NULL" in stp.stp_last_error()
+
+
+def test_server_argument_checks(stp):
+    """Argument validation of the serving entry points happens before any
+    device call."""
+    out = ctypes.c_void_p()
+    assert stp._lib.stp_server_create(0, 4, 1, None, ctypes.byref(out)) == stp.STP_E_INVALID_ARG
+    assert stp._lib.stp_server_create(1 << 30, 0, 1, None, ctypes.byref(out)) == stp.STP_E_INVALID_ARG
+    assert stp._lib.stp_server_create(1 << 30, 4, 65, None, ctypes.byref(out)) == stp.STP_E_INVALID_ARG
+    assert stp._lib.stp_server_create(1 << 30, 4, 1, None, None) == stp.STP_E_INVALID_ARG
+    rid = ctypes.c_uint64()
+    req = stp.stp_request(4, 4, stp.STP_FP64, 1e-8, None, None, None, 0)
+    assert stp._lib.stp_server_submit(None, ctypes.byref(req), ctypes.byref(rid)) == stp.STP_E_INVALID_ARG
+    assert stp._lib.stp_server_poll(None, 1, None, None) == stp.STP_E_INVALID_ARG
+    assert stp._lib.stp_server_drain(None) == stp.STP_E_INVALID_ARG
+    assert stp._lib.stp_server_info(None, None) == stp.STP_E_INVALID_ARG
+    assert stp._lib.stp_server_destroy(None) == stp.STP_OK
