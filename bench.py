@@ -25,6 +25,8 @@ WORKLOADS = {
     "heat2d_J12_K9": (12, 9, 1, 2, "sin"),
     "heat2d_J8_K7_B64": (8, 7, 64, 1000, "random4"),
     "heat2d_J4_K4": (4, 4, 1, None, "sin"),
+    # request stream of uneven sizes (J in 6..11, K in 5..9), see run_serving
+    "heat2d_serve": None,
 }
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
@@ -44,6 +46,14 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="skip the other-precision run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-seconds", type=float, default=20.0)
+    ap.add_argument("--requests", type=int, default=200, help="serving: open-loop requests")
+    ap.add_argument("--calibration-requests", type=int, default=40,
+                    help="serving: closed-loop requests that measure the saturated rate")
+    ap.add_argument("--load", type=float, default=0.8,
+                    help="serving: arrival rate as a fraction of the saturated rate")
+    ap.add_argument("--budget-gb", type=float, default=120.0, help="serving: device budget")
+    ap.add_argument("--slots", type=int, default=4, help="serving: concurrent groups")
+    ap.add_argument("--batch", type=int, default=4, help="serving: requests per group")
     return ap.parse_args()
 
 
@@ -153,6 +163,116 @@ def cpu_baseline(seconds_budget):
     }
 
 
+def serve_stream(stp, torch, server, reqs, prec, rate):
+    """Submit `reqs` (all at once when rate is None, else at Poisson arrival
+    times of that rate), wait for all; returns per-request results and the
+    span from the first submission to the last completion."""
+    import synth
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    arrivals, t = [], 0.0
+    for r in reqs:
+        t += 0.0 if rate is None else r["gap"] / rate
+        arrivals.append(t)
+    inflight, results = {}, []
+    i = 0
+    t0 = time.perf_counter()
+    while i < len(reqs) or inflight:
+        now = time.perf_counter() - t0
+        while i < len(reqs) and now >= arrivals[i]:
+            r = reqs[i]
+            g = synth.fourier_g_torch(r["J"], r["K"], r["seed"], dev).reshape(-1)
+            u0 = torch.as_tensor(synth.smooth_u0(r["K"], r["seed"]).reshape(-1), device=dev)
+            stream.synchronize()  # the server reads g and u0 on its own streams
+            rid = stp.stp_server_submit(server, r["J"], r["K"], prec, r["tol"], u0, g, None)
+            inflight[rid] = (r, g, u0)
+            i += 1
+            now = time.perf_counter() - t0
+        for rid in list(inflight):
+            try:
+                res = stp.stp_server_poll(server, rid)
+            except stp.StpError as e:  # a failed request is reported, not fatal
+                r = inflight.pop(rid)[0]
+                print(f"# request J={r['J']} K={r['K']} tol={r['tol']:.2e} seed={r['seed']} "
+                      f"failed: {e}", file=sys.stderr, flush=True)
+                results.append((r, (e.status, {"iterations": 0}, float("nan"))))
+                continue
+            if res is not None:
+                results.append((inflight.pop(rid)[0], res))
+        time.sleep(0.0005)
+    return results, time.perf_counter() - t0
+
+
+def run_serving(args, stp, torch):
+    import numpy as np
+
+    import synth
+
+    prec = stp.STP_MIXED if args.precision == "mixed" else stp.STP_FP64
+    warm = synth.serving_stream(12, seed=12343)
+    cal = synth.serving_stream(args.calibration_requests, seed=12344)
+    reqs = synth.serving_stream(args.requests, seed=12345)
+    server = stp.stp_server_create(int(args.budget_gb * 1e9), max_slots=args.slots,
+                                   max_batch=args.batch)
+    try:
+        serve_stream(stp, torch, server, warm, prec, None)  # code loading, allocator warm-up
+        res_cal, span_cal = serve_stream(stp, torch, server, cal, prec, None)
+        saturated = len(res_cal) / span_cal
+        rate = args.load * saturated
+        print(f"# serving: closed loop {len(res_cal)} requests in {span_cal:.2f} s "
+              f"({saturated:.2f} solves/s); open loop at {rate:.2f} requests/s",
+              file=sys.stderr, flush=True)
+        res, span = serve_stream(stp, torch, server, reqs, prec, rate)
+        info = stp.stp_server_info(server)
+    finally:
+        stp.stp_server_destroy(server)
+    def size(q):
+        return (2 ** q["J"] + 1) * (2 ** q["K"] - 1) ** 2
+
+    ok = [x for x in res if x[1][0] >= 0]
+    lat = np.array([latency for _, (_, _, latency) in ok])
+    work = sum(size(q) * st["iterations"] for q, (_, st, _) in res)
+    unknowns = sum(size(q) for q, _ in res)
+    statuses = sorted({status for _, (status, _, _) in res})
+    serving = {
+        "requests": len(res),
+        "rate_per_s": round(rate, 3),
+        "saturated_solves_per_s": round(saturated, 3),
+        "solves_per_s": round(len(res) / span, 3),
+        "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+        "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+        "mean_latency_s": round(float(lat.mean()), 4),
+        "span_s": round(span, 3),
+        "mean_group_size": round(info["requests_started"] / max(info["groups_started"], 1), 3),
+        "peak_device_bytes": info["peak_bytes"],
+        "statuses": statuses,
+        "failed": len(res) - len(ok),
+    }
+    line = {
+        "metric": METRIC,
+        "value": work / span,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": round(span * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if prec == stp.STP_MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": "heat2d_serve", "requests": len(res), "unknowns_total": unknowns,
+                   "J": "6..11", "K": "5..9", "rel_tol": "1e-10..1e-6", "precision": args.precision,
+                   "load": args.load, "slots": args.slots, "batch": args.batch,
+                   "budget_gb": args.budget_gb, "parallelism": "single-gpu"},
+        "roofline": None,
+        "cpu_baseline": None,
+        "serving": serving,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -162,6 +282,9 @@ def main():
     import torch
 
     import paper_2009_08875_amd as stp
+
+    if args.workload == "heat2d_serve":
+        return run_serving(args, stp, torch)
 
     J, K, nrhs, seed, u0kind = WORKLOADS[args.workload]
     prec = stp.STP_FP64 if args.precision == "fp64" else stp.STP_MIXED

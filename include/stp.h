@@ -156,8 +156,9 @@ stp_status stp_profile_read(stp_ctx* ctx, int kernel, stp_kernel_stat* out);
  * when it is created.  Requests wait in arrival order; when a slot is free and
  * the head request's context (stp_footprint) fits in the budget, the worker
  * admits it together with up to max_batch - 1 waiting requests of the same
- * (J, K, precision), as the right-hand sides of one batched context (groups of
- * 1, 2, 4, ... requests).  Running groups advance independently, one PCG
+ * (J, K, precision) whose tolerance is within a factor of 10 of its own, as
+ * the right-hand sides of one batched context (groups of 1, 2, 4, ...
+ * requests).  Running groups advance independently, one PCG
  * iteration or refinement step at a time, on separate streams, so requests
  * admitted while others run overlap with them on the device.  Every
  * right-hand side of a group computes exactly its solo solve (its own

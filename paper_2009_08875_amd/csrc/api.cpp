@@ -44,11 +44,15 @@ stp_options resolve(const stp_options* o) {
 // ------------------------------------------------------------ memory plan
 //
 // Every device allocation of a context goes through Arena so that the same
-// code computes the footprint (dry run) and allocates.
+// code computes the footprint (dry run) and allocates.  New memory is zeroed
+// on the context's stream: a plain hipMemset runs on the null stream, which
+// a non-blocking stream does not wait for, so the context's first kernels
+// could otherwise run before the zeroing.
 struct Arena {
   bool dry = true;
   size_t bytes = 0;
   std::vector<void*>* list = nullptr;
+  hipStream_t stream = nullptr;
   template <typename T>
   stp_status get(T** p, int64_t count) {
     size_t b = ((size_t)count * sizeof(T) + 511) & ~(size_t)511;
@@ -65,9 +69,9 @@ struct Arena {
       return STP_E_OUT_OF_MEMORY;
     }
     list->push_back(q);
-    e = hipMemset(q, 0, b);
+    e = hipMemsetAsync(q, 0, b, stream);
     if (e != hipSuccess) {
-      set_error(std::string("hipMemset: ") + hipGetErrorString(e));
+      set_error(std::string("hipMemsetAsync: ") + hipGetErrorString(e));
       return STP_E_DEVICE;
     }
     *p = (T*)q;
@@ -582,6 +586,7 @@ stp_status ensure_ops(stp_ctx* c, Ops<T>& o) {
   Arena ar;
   ar.dry = false;
   ar.list = &c->allocations;
+  ar.stream = c->stream;
   STP_TRY(plan_ops(ar, o, c->K, c->rows, c->vec));
   c->bytes += ar.bytes;
   return STP_OK;
@@ -715,6 +720,7 @@ stp_status stp_create(int J, int K, int nrhs, int precision, const stp_options* 
   Arena ar;
   ar.dry = false;
   ar.list = &c->allocations;
+  ar.stream = c->stream;
   stp_status st = plan_context(ar, c);
   if (st < 0) return fail(st);
   c->bytes = ar.bytes;
@@ -931,6 +937,7 @@ extern "C" stp_status stp_apply(stp_ctx* c, int op, int precision, int rhs, cons
     Arena ar;
     ar.dry = false;
     ar.list = &c->allocations;
+    ar.stream = c->stream;
     STP_TRY(ar.get(&c->apply_buf, 4 * c->per_rhs));
     c->bytes += ar.bytes;
   }

@@ -4,8 +4,8 @@
 // worker thread.  Requests wait in arrival order.  Whenever a slot is free and
 // the head request's context fits in the budget, the worker admits it,
 // together with up to max_batch - 1 waiting requests of the same (J, K,
-// precision): they become the right-hand sides of one batched context, so
-// every operator of the group is one launch.  Admitted groups run at the
+// precision) and a similar tolerance: they become the right-hand sides of
+// one batched context, so every operator of the group is one launch.  Admitted groups run at the
 // same time on different streams: the worker advances every group by one
 // unit of device work (one PCG iteration, or a refinement step) as soon as
 // its previous unit has completed, so work of groups admitted at different
@@ -181,11 +181,15 @@ void admit(stp_server* s) {
       std::lock_guard<std::mutex> lk(s->mu);
       if (s->waiting.empty()) return;
       const stp_request& h = s->waiting.front()->req;
-      // same-shape requests join the head request, up to max_batch of them
+      // requests of the same shape and a tolerance within a factor of 10 of
+      // the head's (so the group's right-hand sides need similar iteration
+      // counts) join the head request, up to max_batch of them
       std::vector<size_t> idx{0};
       for (size_t i = 1; i < s->waiting.size() && (int)idx.size() < s->max_batch; ++i) {
         const stp_request& q = s->waiting[i]->req;
-        if (q.J == h.J && q.K == h.K && q.precision == h.precision) idx.push_back(i);
+        if (q.J == h.J && q.K == h.K && q.precision == h.precision &&
+            q.rel_tol <= 10.0 * h.rel_tol && h.rel_tol <= 10.0 * q.rel_tol)
+          idx.push_back(i);
       }
       int nb = pow2_floor((int)idx.size());
       while (nb > 1 && !fits(s, h.J, h.K, h.precision, nb)) nb /= 2;

@@ -126,3 +126,20 @@ WORKLOADS = {
     "heat2d_J12_K9": dict(J=12, K=9, nrhs=1, g_seed=2, u0="sin"),
     "heat2d_J8_K7_B64": dict(J=8, K=7, nrhs=64, g_seed=1000, u0="random4"),
 }
+
+
+def serving_stream(n: int, seed: int = 12345, J_range=(6, 11), K_range=(5, 9),
+                   log10_tol_range=(-10.0, -6.0)):
+    """A stream of ``n`` solve requests of uneven sizes: ``J`` and ``K``
+    uniform over their ranges (so ``N_t`` and ``h`` are log-uniform),
+    ``tol = 10**U(log10_tol_range)``, and for each request a data seed
+    ``50000 + index`` (forcing from :func:`fourier_g`, initial value from
+    :func:`smooth_u0`).  Also returns unit-rate exponential inter-arrival gaps;
+    divide them by the arrival rate to get a Poisson process."""
+    rng = np.random.default_rng(seed)
+    J = rng.integers(J_range[0], J_range[1] + 1, size=n)
+    K = rng.integers(K_range[0], K_range[1] + 1, size=n)
+    tol = 10.0 ** rng.uniform(log10_tol_range[0], log10_tol_range[1], size=n)
+    gaps = rng.exponential(1.0, size=n)
+    return [dict(J=int(J[i]), K=int(K[i]), tol=float(tol[i]), seed=50000 + i, gap=float(gaps[i]))
+            for i in range(n)]

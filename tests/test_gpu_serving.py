@@ -102,6 +102,32 @@ def test_each_result_is_the_same_alone_and_in_the_mix(stp):
         assert rel_err(u, u_solo) <= (1e-12 if prec == "FP64" else 1e-9)
 
 
+def test_many_new_contexts_concurrently(stp):
+    """Sixteen requests of distinct shapes submitted at once: every admission
+    creates a context while others run on the server's other streams.  Each
+    result equals its solo solve (iteration count and values)."""
+    say("serving: concurrent context creation")
+    shapes = [(J, K) for J in (1, 2, 3, 4) for K in (2, 3, 4, 5)]
+    server = stp.stp_server_create(8 << 30, max_slots=4, max_batch=1)
+    try:
+        ids, outs, data = [], [], []
+        for k, (J, K) in enumerate(shapes):
+            g, u0 = _data(J, K, 600 + k)
+            u = np.zeros(g.size)
+            data.append((g, u0))
+            outs.append(u)
+            ids.append(stp.stp_server_submit(server, J, K, stp.STP_MIXED, 1e-8, flat(u0), flat(g), u))
+        res = _wait(stp, server, ids)
+    finally:
+        stp.stp_server_destroy(server)
+    for (J, K), rid, u, (g, u0) in zip(shapes, ids, outs, data):
+        status, st, _ = res[rid]
+        s_status, s_st, u_solo = _solo(stp, J, K, stp.STP_MIXED, 1e-8, g, u0)
+        assert status == s_status == stp.STP_OK, (J, K)
+        assert st["iterations"] == s_st["iterations"], (J, K)
+        assert rel_err(u, u_solo) <= 1e-9, (J, K)
+
+
 def test_served_result_matches_oracle(stp):
     J, K, seed = 3, 4, 301
     say("serving: result vs oracle")
