@@ -97,11 +97,12 @@ def run_solves(stp, ctx, nrhs, tol, steps, warmup, torch, profile=False):
     return (t1 - t0) / steps, stats, kstats
 
 
-def measured_traffic(workload, precision, kernel):
+def measured_traffic(workload, precision, kernel, alg_bytes_per_launch):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by the copy-kernel
-    calibration), or None when no summary exists for this workload or the
-    kernel source has changed since the counters were taken."""
+    calibration), or None when no summary exists for this workload, the
+    kernel source has changed since the counters were taken, or the launches
+    differ from the measured ones (other algorithmic bytes per launch)."""
     import hashlib
     import re
 
@@ -115,6 +116,8 @@ def measured_traffic(workload, precision, kernel):
     src = os.path.join(ROOT, "paper_2009_08875_amd", "csrc", rec["source"])
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if digest != rec["sha256"]:
+        return None
+    if abs(rec["alg_bytes_per_launch"] - alg_bytes_per_launch) > 1e-3 * alg_bytes_per_launch:
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -318,8 +321,8 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic(args.workload, args.precision,
-                                    stp.STP_KERNEL_NAMES[dom]),
+        "traffic": measured_traffic(args.workload, args.precision, stp.STP_KERNEL_NAMES[dom],
+                                    bytes_per_launch),
         "avg_launch_ms": round(avg_ms, 4),
         "alg_bytes_per_launch": bytes_per_launch,
         "launches": d["launches"],

@@ -97,7 +97,8 @@ stp_status plan_ops(Arena& ar, Ops<T>& o, int K, int64_t rows, int64_t vec) {
   STP_TRY(ar.get(&o.X, vec));
   STP_TRY(ar.get(&o.y, 2 * vec));
   STP_TRY(ar.get(&o.z, 2 * vec));
-  STP_TRY(plan_mg(ar, o.mg, K, std::min<int64_t>(rows, kMaxGridY)));
+  // S and f apply K_x to two arrays at once (2 * rows rows in one launch)
+  STP_TRY(plan_mg(ar, o.mg, K, std::min<int64_t>(2 * rows, kMaxGridY)));
   o.ready = !ar.dry;
   return STP_OK;
 }
@@ -288,8 +289,8 @@ stp_status S_apply(stp_ctx* c, Ops<T>& o, const T* X, T* out, int nrhs) {
   T* z1 = o.z;
   T* z2 = o.z + v;
   HIP_TRY(time_stencil_pair<T>(c->stream, X, y1, y2, c->J, c->K, nrhs));
-  STP_TRY(mg_apply<T>(c, o.mg, y1, z1, rows, 1.0, nullptr));
-  STP_TRY(mg_apply<T>(c, o.mg, y2, z2, rows, 1.0, nullptr));
+  // y1 | y2 and z1 | z2 are contiguous: one K_x application over both
+  STP_TRY(mg_apply<T>(c, o.mg, y1, z1, 2 * rows, 1.0, nullptr));
   HIP_TRY(combine<T>(c->stream, z1, z2, X, c->per_rhs, out, c->J, c->K, nrhs));
   return STP_OK;
 }
@@ -328,8 +329,7 @@ stp_status rhs_apply(stp_ctx* c, double* f) {
     double* G1 = o.y;
     double* G0 = o.y + v;
     HIP_TRY(rhs_stencil_pair<double>(c->stream, c->g, G1, G0, c->J, c->K, c->nrhs));
-    STP_TRY(mg_apply<double>(c, o.mg, G1, z1, c->rows, 1.0, nullptr));
-    STP_TRY(mg_apply<double>(c, o.mg, G0, z2, c->rows, 1.0, nullptr));
+    STP_TRY(mg_apply<double>(c, o.mg, G1, z1, 2 * c->rows, 1.0, nullptr));  // G1 | G0 -> z1 | z2
   } else {
     HIP_TRY(hipMemsetAsync(z1, 0, sizeof(double) * 2 * v, c->stream));
   }

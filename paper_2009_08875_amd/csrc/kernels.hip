@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 
 #include "kernels.h"
 
@@ -15,6 +16,8 @@ namespace stp {
 namespace {
 
 constexpr int kBlock = 256;
+
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 inline unsigned blocks_for(int64_t count, int per_block = kBlock) {
   return (unsigned)((count + per_block - 1) / per_block);
@@ -154,6 +157,47 @@ __device__ inline double block_sum(double v) {
   return t;
 }
 
+// 16 bytes of T: the widest load a lane issues (four floats or two doubles).
+template <typename T>
+struct alignas(16) Vec16 {
+  static constexpr int W = 16 / (int)sizeof(T);
+  T e[W];
+};
+
+// Partial sums of a . b over 16-byte vectors, two independent loads per
+// thread and step to keep more bytes in flight; n is a multiple of the
+// vector width and the segments are 16-byte aligned (checked by the launcher).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void dot_partial_vec_kernel(const T* __restrict__ a,
+                                                                 const T* __restrict__ b,
+                                                                 int64_t n,
+                                                                 double* __restrict__ partials) {
+  using V = Vec16<T>;
+  const int nblk = gridDim.x;
+  const int64_t seg = (int64_t)blockIdx.y * n;
+  const V* av = reinterpret_cast<const V*>(a + seg);
+  const V* bv = reinterpret_cast<const V*>(b + seg);
+  const int64_t nv = n / V::W;
+  const int64_t stride = (int64_t)nblk * kBlock;
+  double acc0 = 0.0, acc1 = 0.0;
+  int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  for (; i + stride < nv; i += 2 * stride) {
+    const V x0 = av[i], y0 = bv[i], x1 = av[i + stride], y1 = bv[i + stride];
+#pragma unroll
+    for (int w = 0; w < V::W; ++w) {
+      acc0 += (double)x0.e[w] * (double)y0.e[w];
+      acc1 += (double)x1.e[w] * (double)y1.e[w];
+    }
+  }
+  if (i < nv) {
+    const V x0 = av[i], y0 = bv[i];
+#pragma unroll
+    for (int w = 0; w < V::W; ++w) acc0 += (double)x0.e[w] * (double)y0.e[w];
+  }
+  const double acc = block_sum(acc0 + acc1);
+  if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * nblk + blockIdx.x] = acc;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void dot_partial_kernel(const T* __restrict__ a,
                                                              const T* __restrict__ b, int64_t n,
@@ -178,6 +222,13 @@ __global__ __launch_bounds__(kBlock) void dot_final_kernel(const double* __restr
 // ------------------------------------------------------------ vector updates
 
 template <typename T>
+__global__ __launch_bounds__(kBlock) void copy_vec_kernel(const Vec16<T>* __restrict__ s,
+                                                          Vec16<T>* __restrict__ d, int64_t nv) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < nv) d[i] = s[i];
+}
+
+template <typename T>
 __global__ __launch_bounds__(kBlock) void copy_kernel(const T* __restrict__ s, T* __restrict__ d,
                                                       int64_t count) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -196,6 +247,46 @@ __global__ __launch_bounds__(kBlock) void update_wr_kernel(T* __restrict__ w, T*
   const int64_t k = (int64_t)blockIdx.y * n + i;
   w[k] = (T)((double)w[k] + g * (double)p[k]);
   r[k] = (T)((double)r[k] - g * (double)q[k]);
+}
+
+// Vector forms of the two updates: 16 bytes per lane and array; n is a
+// multiple of the vector width and every array is 16-byte aligned.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void update_wr_vec_kernel(Vec16<T>* __restrict__ w,
+                                                               Vec16<T>* __restrict__ r,
+                                                               const Vec16<T>* __restrict__ p,
+                                                               const Vec16<T>* __restrict__ q,
+                                                               const double* __restrict__ gamma,
+                                                               int64_t nv) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nv) return;
+  const double g = gamma[blockIdx.y];
+  const int64_t k = (int64_t)blockIdx.y * nv + i;
+  Vec16<T> wv = w[k], rv = r[k];
+  const Vec16<T> pv = p[k], qv = q[k];
+#pragma unroll
+  for (int e = 0; e < Vec16<T>::W; ++e) {
+    wv.e[e] = (T)((double)wv.e[e] + g * (double)pv.e[e]);
+    rv.e[e] = (T)((double)rv.e[e] - g * (double)qv.e[e]);
+  }
+  w[k] = wv;
+  r[k] = rv;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void update_p_vec_kernel(Vec16<T>* __restrict__ p,
+                                                              const Vec16<T>* __restrict__ z,
+                                                              const double* __restrict__ beta,
+                                                              int64_t nv) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nv) return;
+  const double bt = beta[blockIdx.y];
+  const int64_t k = (int64_t)blockIdx.y * nv + i;
+  Vec16<T> pv = p[k];
+  const Vec16<T> zv = z[k];
+#pragma unroll
+  for (int e = 0; e < Vec16<T>::W; ++e) pv.e[e] = (T)((double)zv.e[e] + bt * (double)pv.e[e]);
+  p[k] = pv;
 }
 
 template <typename T>
@@ -435,13 +526,23 @@ template <typename T>
 hipError_t dot(hipStream_t s, const T* a, const T* b, int64_t n, int nrhs, double* partials,
                double* out) {
   const int nblk = dot_blocks(n);
-  dot_partial_kernel<T><<<dim3(nblk, nrhs), kBlock, 0, s>>>(a, b, n, partials);
+  if (n % Vec16<T>::W == 0 && aligned16(a) && aligned16(b))
+    dot_partial_vec_kernel<T><<<dim3(nblk, nrhs), kBlock, 0, s>>>(a, b, n, partials);
+  else
+    dot_partial_kernel<T><<<dim3(nblk, nrhs), kBlock, 0, s>>>(a, b, n, partials);
   dot_final_kernel<<<nrhs, kBlock, 0, s>>>(partials, nblk, out);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t copy(hipStream_t s, const T* src, T* dst, int64_t count) {
+  constexpr int W = Vec16<T>::W;
+  if (count % W == 0 && aligned16(src) && aligned16(dst)) {
+    const int64_t nv = count / W;
+    copy_vec_kernel<T><<<blocks_for(nv), kBlock, 0, s>>>(
+        reinterpret_cast<const Vec16<T>*>(src), reinterpret_cast<Vec16<T>*>(dst), nv);
+    return hipGetLastError();
+  }
   copy_kernel<T><<<blocks_for(count), kBlock, 0, s>>>(src, dst, count);
   return hipGetLastError();
 }
@@ -449,12 +550,25 @@ hipError_t copy(hipStream_t s, const T* src, T* dst, int64_t count) {
 template <typename T>
 hipError_t update_wr(hipStream_t s, T* w, T* r, const T* p, const T* q, const double* gamma,
                      int64_t n, int nrhs) {
+  if (n % Vec16<T>::W == 0 && aligned16(w) && aligned16(r) && aligned16(p) && aligned16(q)) {
+    const int64_t nv = n / Vec16<T>::W;
+    update_wr_vec_kernel<T><<<dim3(blocks_for(nv), nrhs), kBlock, 0, s>>>(
+        reinterpret_cast<Vec16<T>*>(w), reinterpret_cast<Vec16<T>*>(r),
+        reinterpret_cast<const Vec16<T>*>(p), reinterpret_cast<const Vec16<T>*>(q), gamma, nv);
+    return hipGetLastError();
+  }
   update_wr_kernel<T><<<dim3(blocks_for(n), nrhs), kBlock, 0, s>>>(w, r, p, q, gamma, n);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t update_p(hipStream_t s, T* p, const T* z, const double* beta, int64_t n, int nrhs) {
+  if (n % Vec16<T>::W == 0 && aligned16(p) && aligned16(z)) {
+    const int64_t nv = n / Vec16<T>::W;
+    update_p_vec_kernel<T><<<dim3(blocks_for(nv), nrhs), kBlock, 0, s>>>(
+        reinterpret_cast<Vec16<T>*>(p), reinterpret_cast<const Vec16<T>*>(z), beta, nv);
+    return hipGetLastError();
+  }
   update_p_kernel<T><<<dim3(blocks_for(n), nrhs), kBlock, 0, s>>>(p, z, beta, n);
   return hipGetLastError();
 }

@@ -36,16 +36,21 @@
 // rows so that every resident wave gets the same number of row steps; a
 // segment that does not start at the bottom of the grid restarts the
 // pipeline H rows lower (rounded down to the 12-row unroll), recomputing
-// those rows without writing them.
+// those rows without writing them.  How many segments (one per time row, or
+// about as many as fit the resident waves) is picked per level and row count
+// by the launch autotuner; all give the same result.
 //
 // Kernels.  pre:  x <- forward steps from xin (or zero), residual, restriction
 //                 b_c <- P^T (b - C x);   writes x and b_c.
 //           post: x <- backward steps from xin + P e_c;   writes x, or A x.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
+#include <vector>
 
 #include "kernels.h"
+#include "tune.h"
 
 namespace stp {
 
@@ -691,19 +696,33 @@ hipError_t launch(hipStream_t s, const T* xin, const T* b, const T* ec, T* xout,
   if (slots < 0) slots = resident_waves(kernel);
   const int n = grid_n(l);
   const int ns = strip_count(n, H);
-  // one group per time row, or as many groups as fit in the resident slots
-  // when rows outnumber them and the segments stay long compared with the
-  // restart halo
-  int64_t groups = rows;
-  if (slots > 0) {
-    const int64_t g = slots / ns;
-    if (g > 0 && rows > g && (int64_t)rows * n / g >= 8 * (H + kWin)) groups = g;
+  // Candidate group counts (all give the same result): G groups that split
+  // the rows into equal segments, for G = the groups that fit in the
+  // resident slots (the first candidate, used untuned), 3/4, 1/2, 1/4 and
+  // twice that, as long as the segments stay long compared with the restart
+  // halo; and one group per time row.  Fewer groups than resident slots can
+  // win: fewer grid lines are then streamed at once.
+  std::vector<int64_t> cand;
+  const int64_t fit = slots > 0 ? slots / ns : 0;
+  for (int64_t g : {fit, 3 * fit / 4, fit / 2, fit / 4, 2 * fit}) {
+    if (g > 0 && rows > g && (int64_t)rows * n / g >= 8 * (H + kWin) &&
+        std::find(cand.begin(), cand.end(), g) == cand.end())
+      cand.push_back(g);
   }
-  const int64_t waves = groups * ns;
-  const unsigned blocks = (unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-  kernel<<<blocks, 64 * kWavesPerBlock, 0, s>>>(xin, b, ec, xout, bc, l, ns, rows, (int)groups, a,
-                                                sigma);
-  return hipGetLastError();
+  cand.push_back(rows);
+  auto go = [&](int c) -> hipError_t {
+    const int64_t groups = cand[c];
+    const int64_t waves = groups * ns;
+    const unsigned blocks = (unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    kernel<<<blocks, 64 * kWavesPerBlock, 0, s>>>(xin, b, ec, xout, bc, l, ns, rows, (int)groups,
+                                                  a, sigma);
+    return hipGetLastError();
+  };
+  const uint64_t variant = (sizeof(T) == 8 ? 16 : 0) | (PRE ? 8 : 0) | (XIN ? 4 : 0) |
+                           (DIAG ? 2 : 0) | (WRITE_A ? 1 : 0);
+  const int c = tuned(tune_key(1, variant, (uint64_t)l, (uint64_t)rows), (int)cand.size(), 0, s,
+                      go);
+  return go(c);
 }
 
 }  // namespace

@@ -8,10 +8,12 @@
 // (A_x: 5 points, M_x: 7 points on the "/" mesh) read them back.  Every input
 // element is read from HBM once per tile (plus the halo and one time row at
 // each end of a chunk).  Workgroups are numbered so that neighbouring tiles
-// run on the same XCD and share its L2 for the halos.
+// run on the same XCD and share its L2 for the halos.  The chunk length (8 to
+// 64 time rows) is picked per problem shape by the launch autotuner.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
+#include "tune.h"
 
 namespace stp {
 
@@ -22,7 +24,7 @@ constexpr int kHX = kTX + 2, kHY = kTY + 2;     // tile with halo
 constexpr int kHalo = kHX * kHY;                // 1188 nodes
 constexpr int kThreads = 256;
 constexpr int kPer = (kHalo + kThreads - 1) / kThreads;  // halo nodes per thread (5)
-constexpr int kRowChunk = 32;                   // time rows per workgroup
+constexpr int kChunks[] = {8, 16, 32, 64};      // candidate time rows per workgroup
 
 enum Mode { kTimePair = 0, kRhsPair = 1, kCombine = 2 };
 
@@ -77,7 +79,7 @@ template <typename T, int MODE>
 __global__ __launch_bounds__(kThreads) void row_stencil_kernel(
     const T* __restrict__ in0, const T* __restrict__ in1, const T* __restrict__ extra,
     int64_t extra_stride, T* __restrict__ out0, T* __restrict__ out1, int J, int K, int tiles_x,
-    int tiles, int chunks) {
+    int tiles, int chunks, int chunk_rows) {
   __shared__ T s0[kHalo], s1[kHalo], s2[kHalo], s3[kHalo];
   const int nb = tiles * chunks;
   const int lb = xcd_remap(blockIdx.x, nb);
@@ -112,8 +114,8 @@ __global__ __launch_bounds__(kThreads) void row_stencil_kernel(
     return goff[p] >= 0 ? a[base + (int64_t)row * slab + goff[p]] : T(0);
   };
 
-  const int i0 = chunk * kRowChunk;
-  const int i1 = min(i0 + kRowChunk, N + 1);
+  const int i0 = chunk * chunk_rows;
+  const int i1 = min(i0 + chunk_rows, N + 1);
   T xm[kPer], x0[kPer], xp[kPer];
   if constexpr (MODE != kCombine) {
 #pragma unroll
@@ -192,10 +194,17 @@ hipError_t launch_rows(hipStream_t s, const T* in0, const T* in1, const T* extra
   const int n = grid_n(K);
   const int tiles_x = (n + kTX - 1) / kTX, tiles_y = (n + kTY - 1) / kTY;
   const int tiles = tiles_x * tiles_y;
-  const int chunks = ((1 << J) + 1 + kRowChunk - 1) / kRowChunk;
-  row_stencil_kernel<T, MODE><<<dim3(tiles * chunks, nrhs), kThreads, 0, s>>>(
-      in0, in1, extra, extra_stride, out0, out1, J, K, tiles_x, tiles, chunks);
-  return hipGetLastError();
+  auto go = [&](int c) -> hipError_t {
+    const int cr = kChunks[c];
+    const int chunks = ((1 << J) + 1 + cr - 1) / cr;
+    row_stencil_kernel<T, MODE><<<dim3(tiles * chunks, nrhs), kThreads, 0, s>>>(
+        in0, in1, extra, extra_stride, out0, out1, J, K, tiles_x, tiles, chunks, cr);
+    return hipGetLastError();
+  };
+  const uint64_t variant = (sizeof(T) == 8 ? 4 : 0) | (uint64_t)MODE;
+  const int c = tuned(tune_key(2, variant, (uint64_t)(J * 16 + K), (uint64_t)nrhs),
+                      (int)(sizeof(kChunks) / sizeof(kChunks[0])), 2, s, go);
+  return go(c);
 }
 
 }  // namespace

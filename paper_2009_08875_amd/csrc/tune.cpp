@@ -1,0 +1,71 @@
+// Launch-shape autotuner (see tune.h).
+#include "tune.h"
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+namespace stp {
+
+namespace {
+
+std::mutex g_mu;
+std::map<uint64_t, int> g_choice;
+
+bool env_flag(const char* name, bool dflt) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  return std::strcmp(v, "0") != 0;
+}
+
+}  // namespace
+
+int tuned(uint64_t key, int candidates, int fallback, hipStream_t stream,
+          const std::function<hipError_t(int)>& launch) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_choice.find(key);
+    if (it != g_choice.end()) return it->second;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    return fallback;
+  static const bool enabled = env_flag("STP_TUNE", true);
+  static const bool log = env_flag("STP_TUNE_LOG", false);
+  int best = fallback;
+  if (enabled && candidates > 1) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+      std::vector<float> ms(candidates, -1.0f);
+      float best_ms = 0.0f;
+      for (int c = 0; c < candidates; ++c) {
+        if (launch(c) != hipSuccess) continue;  // warm-up run
+        if (hipEventRecord(e0, stream) != hipSuccess || launch(c) != hipSuccess ||
+            launch(c) != hipSuccess || hipEventRecord(e1, stream) != hipSuccess ||
+            hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms[c], e0, e1) != hipSuccess)
+          continue;
+        if (best_ms == 0.0f || ms[c] < best_ms) {
+          best_ms = ms[c];
+          best = c;
+        }
+      }
+      if (log) {
+        std::fprintf(stderr, "[stp tune] key %016llx:", (unsigned long long)key);
+        for (int c = 0; c < candidates; ++c) std::fprintf(stderr, " %d:%.3fms", c, ms[c] / 2);
+        std::fprintf(stderr, " -> %d\n", best);
+      }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipGetLastError();
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_choice[key] = best;
+  return best;
+}
+
+}  // namespace stp
