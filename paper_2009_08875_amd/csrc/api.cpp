@@ -122,7 +122,7 @@ stp_status plan_context(Arena& ar, stp_ctx* c) {
   STP_TRY(ar.get(&c->fhat, vec));
   STP_TRY(ar.get(&c->u, vec));
   STP_TRY(ar.get(&c->sigma, c->rows));
-  STP_TRY(ar.get(&c->partials, (int64_t)c->nrhs * 1024));
+  STP_TRY(ar.get(&c->partials, (int64_t)c->nrhs * std::max(1024, analysis_dot_blocks(c->K))));
   STP_TRY(ar.get(&c->tolv, c->nrhs));
   STP_TRY(ar.get(&c->sc.rho, c->nrhs));
   STP_TRY(ar.get(&c->sc.rho0, c->nrhs));
@@ -298,11 +298,20 @@ stp_status S_apply(stp_ctx* c, Ops<T>& o, const T* X, T* out, int nrhs) {
 // out = S-hat p = W^T S W p (eq. (11)).
 template <typename T>
 stp_status Shat_apply(stp_ctx* c, Ops<T>& o, const T* p, T* out, int nrhs) {
-  const int64_t v = (int64_t)nrhs * c->per_rhs;
-  HIP_TRY(copy<T>(c->stream, p, o.X, v));
-  HIP_TRY(wavelet<T>(c->stream, o.X, c->J, c->K, nrhs, true));
+  HIP_TRY(synthesis<T>(c->stream, p, o.X, c->J, c->K, nrhs));
   STP_TRY(S_apply<T>(c, o, o.X, out, nrhs));
   HIP_TRY(wavelet<T>(c->stream, out, c->J, c->K, nrhs, false));
+  return STP_OK;
+}
+
+// The S-hat product of a PCG iteration: p = z + beta p (the direction update
+// of the previous iteration, fused into the synthesis), q = S-hat p, and
+// pq = p^T q (fused into the analysis).
+template <typename T>
+stp_status Shat_iteration(stp_ctx* c, Ops<T>& o, PcgVecs<T>& v) {
+  HIP_TRY(synthesis_update<T>(c->stream, v.p, v.z, c->sc.beta, o.X, c->J, c->K, c->nrhs));
+  STP_TRY(S_apply<T>(c, o, o.X, v.q, c->nrhs));
+  HIP_TRY(analysis_dot<T>(c->stream, v.q, v.p, c->partials, c->sc.pq, c->J, c->K, c->nrhs));
   return STP_OK;
 }
 
@@ -361,20 +370,20 @@ stp_status pcg_init(stp_ctx* c, PcgVecs<T>& v, const T* rhs, const double* tol) 
 }
 
 // One PCG iteration for every right-hand side; inactive ones get gamma = 0
-// and keep w and r.  No host synchronisation, no memset: graph-capturable.
+// and keep w and r.  The direction update p = z + beta p of the previous
+// iteration happens at the start of this one (beta = 0 after the start, where
+// p = z already).  No host synchronisation, no memset: graph-capturable.
 template <typename T>
 stp_status pcg_iteration(stp_ctx* c, PcgVecs<T>& v) {
   Ops<T>& o = ops_of<T>(c);
   const int nrhs = c->nrhs;
   const int64_t n = c->per_rhs;
-  STP_TRY(Shat_apply<T>(c, o, v.p, v.q, nrhs));
-  HIP_TRY(dot<T>(c->stream, v.p, v.q, n, nrhs, c->partials, c->sc.pq));
+  STP_TRY(Shat_iteration<T>(c, o, v));
   HIP_TRY(pcg_gamma(c->stream, c->sc, nrhs));
   HIP_TRY(update_wr<T>(c->stream, v.w, v.r, v.p, v.q, c->sc.gamma, n, nrhs));
   STP_TRY(KX_apply<T>(c, o, v.r, v.z, nrhs));
   HIP_TRY(dot<T>(c->stream, v.r, v.z, n, nrhs, c->partials, c->sc.rhonew));
   HIP_TRY(pcg_beta(c->stream, c->sc, nrhs, c->opt.maxit));
-  HIP_TRY(update_p<T>(c->stream, v.p, v.z, c->sc.beta, n, nrhs));
   return STP_OK;
 }
 
@@ -433,26 +442,25 @@ bool any_active(const stp_ctx* c) {
   return false;
 }
 
-// Last unit: u = W w, and the statistics to pinned host memory.
+// Last unit: u = W w (out of place), and the statistics to pinned host memory.
 stp_status finish_unit(stp_ctx* c) {
   const int nr = c->nrhs;
   double* hs = c->h_stats;
   int* hi = (int*)(c->h_stats + 2 * nr);
   if (c->prec == STP_FP64) {
-    HIP_TRY(copy<double>(c->stream, c->pcg64.w, c->u, c->vec));
+    HIP_TRY(synthesis<double>(c->stream, c->pcg64.w, c->u, c->J, c->K, nr));
     HIP_TRY(hipMemcpyAsync(hs, c->sc.rho, sizeof(double) * nr, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(hs + nr, c->sc.rho0, sizeof(double) * nr, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(hi, c->sc.its, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(hi + nr, c->sc.status, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
   } else {
-    HIP_TRY(copy<double>(c->stream, c->w64, c->u, c->vec));
+    HIP_TRY(synthesis<double>(c->stream, c->w64, c->u, c->J, c->K, nr));
     HIP_TRY(hipMemcpyAsync(hs, c->ms.rel, sizeof(double) * nr, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(hi, c->ms.inner_its, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(hi + nr, c->ms.status, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(hi + 2 * nr, c->ms.outer, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(hi + 3 * nr, c->ms.done, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
   }
-  HIP_TRY(wavelet<double>(c->stream, c->u, c->J, c->K, nr, true));
   HIP_TRY(hipEventRecord(c->ev1, c->stream));
   HIP_TRY(hipEventRecord(c->ev_flags, c->stream));
   c->drv.phase = stp_ctx::kFinish;
@@ -716,6 +724,19 @@ stp_status stp_create(int J, int K, int nrhs, int precision, const stp_options* 
       return fail(STP_E_DEVICE);
     }
     c->own_stream = true;
+  }
+  {
+    // refuse early when the context cannot fit in what the device has free
+    Arena dry;
+    stp_ctx probe;
+    init_dims(&probe, J, K, nrhs, precision);
+    size_t free_b = 0, total_b = 0;
+    if (plan_context(dry, &probe) == STP_OK && hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+        dry.bytes > free_b) {
+      set_error("context needs " + std::to_string(dry.bytes) + " bytes of device memory, " +
+                std::to_string(free_b) + " are free");
+      return fail(STP_E_OUT_OF_MEMORY);
+    }
   }
   Arena ar;
   ar.dry = false;

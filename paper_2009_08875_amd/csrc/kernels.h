@@ -62,6 +62,20 @@ hipError_t apply_M(hipStream_t s, const T* x, T* y, int K, int rows);
 // ---- three-point wavelet transform along time, in place (Section 3.3).
 template <typename T>
 hipError_t wavelet(hipStream_t s, T* X, int J, int K, int nrhs, bool synthesis);
+// dst = W src (src == dst allowed; for J = 0 a copy).
+template <typename T>
+hipError_t synthesis(hipStream_t s, const T* src, T* dst, int J, int K, int nrhs);
+// X = W p after the conjugate-gradient update p = z + beta_b p (p is updated
+// in place; X must not alias p, z).
+template <typename T>
+hipError_t synthesis_update(hipStream_t s, T* p, const T* z, const double* beta, T* X, int J,
+                            int K, int nrhs);
+// X = W^T X in place, and out_b = p_b^T X_b (FP64, deterministic); partials
+// holds nrhs * analysis_dot_blocks(K) values.
+int analysis_dot_blocks(int K);
+template <typename T>
+hipError_t analysis_dot(hipStream_t s, T* X, const T* p, double* partials, double* out, int J,
+                        int K, int nrhs);
 
 // ---- vector operations over `nrhs` segments of `n` elements (segment b at
 // offset b * n).  Dots are deterministic: a fixed block decomposition of each

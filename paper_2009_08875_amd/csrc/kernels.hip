@@ -95,32 +95,87 @@ __global__ __launch_bounds__(kBlock) void apply_AM_kernel(const T* __restrict__ 
 // keeps the old value of the current even node in registers.
 __device__ inline double boundary_weight(int e, int N) { return (e == 0 || e == N) ? 1.0 : 0.5; }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void wavelet_kernel(T* __restrict__ X, int J, int K,
-                                                         bool synthesis) {
+// Synthesis W (coarse to fine), one thread per column of the slab.  At
+// level l the odd multiples m of s = N / 2^l are touched for the first time:
+// their coefficient d is read from src; the even neighbours (multiples of
+// 2s) come from dst, where coarser levels left them (rows 0 and N are first
+// touched at level 1).  src == dst runs in place.  With UPD the first touch
+// of a row also performs the conjugate-gradient update p = z + beta p: src is
+// p, which receives the updated value, and the updated value is transformed.
+template <typename T, bool UPD>
+__global__ __launch_bounds__(kBlock) void wavelet_syn_kernel(const T* src, T* dst, T* p,
+                                                             const T* __restrict__ z,
+                                                             const double* __restrict__ beta,
+                                                             int J, int K) {
   const int64_t slab = slab_elems(K);
   const int64_t col = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (col >= slab) return;
   const int N = 1 << J;
-  T* base = X + (int64_t)blockIdx.y * (N + 1) * slab + col;
-  if (synthesis) {
-    for (int l = 1; l <= J; ++l) {
-      const int s = N >> l;
-      const T c = (T)exp2(0.5 * (double)l);
-      T e_old = base[0];
-      T e_acc = e_old;
-      for (int m = s; m < N; m += 2 * s) {
-        const T d = base[(int64_t)m * slab];
-        const T r_old = base[(int64_t)(m + s) * slab];
-        base[(int64_t)m * slab] = T(0.5) * (e_old + r_old) + c * d;
-        e_acc -= c * T(boundary_weight(m - s, N)) * d;
-        base[(int64_t)(m - s) * slab] = e_acc;
-        e_old = r_old;
-        e_acc = r_old - c * T(boundary_weight(m + s, N)) * d;
-      }
-      base[(int64_t)N * slab] = e_acc;
+  const int64_t off = (int64_t)blockIdx.y * (N + 1) * slab + col;
+  const T* sb = src + off;
+  T* db = dst + off;
+  const double bt = UPD ? beta[blockIdx.y] : 0.0;
+  auto first = [&](int r) -> T {
+    const int64_t o = (int64_t)r * slab;
+    if constexpr (UPD) {
+      const T v = (T)((double)z[off + o] + bt * (double)p[off + o]);
+      p[off + o] = v;
+      return v;
+    } else {
+      return sb[o];
     }
-  } else {
+  };
+  if (J == 0) {
+    const T v0 = first(0), v1 = first(N);
+    db[0] = v0;
+    db[(int64_t)N * slab] = v1;
+    return;
+  }
+  for (int l = 1; l <= J; ++l) {
+    const int s = N >> l;
+    const T c = (T)exp2(0.5 * (double)l);
+    T e_old = l == 1 ? first(0) : db[0];
+    T e_acc = e_old;
+    for (int m = s; m < N; m += 2 * s) {
+      const T d = first(m);
+      const T r_old = l == 1 ? first(N) : db[(int64_t)(m + s) * slab];
+      db[(int64_t)m * slab] = T(0.5) * (e_old + r_old) + c * d;
+      e_acc -= c * T(boundary_weight(m - s, N)) * d;
+      db[(int64_t)(m - s) * slab] = e_acc;
+      e_old = r_old;
+      e_acc = r_old - c * T(boundary_weight(m + s, N)) * d;
+    }
+    db[(int64_t)N * slab] = e_acc;
+  }
+}
+
+// Analysis W^T (fine to coarse), in place, one thread per column.  A row's
+// value is final once it is written as an odd multiple at its level (rows 0
+// and N after level 1).  With DOT each final value is multiplied by p in the
+// same row and summed per column in FP64, the columns of a block are summed
+// in a fixed order, and the block's sum goes to partials (the first pass of
+// the dot product p^T (W^T y)).
+__device__ double block_sum(double v);
+
+template <typename T, bool DOT>
+__global__ __launch_bounds__(kBlock) void wavelet_ana_kernel(T* __restrict__ X,
+                                                             const T* __restrict__ p,
+                                                             double* __restrict__ partials,
+                                                             int J, int K) {
+  const int64_t slab = slab_elems(K);
+  const int64_t col = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int N = 1 << J;
+  const int64_t off = (int64_t)blockIdx.y * (N + 1) * slab + col;
+  double acc = 0.0;
+  if (col < slab) {
+    T* base = X + off;
+    auto fin = [&](int r, T v) {
+      if constexpr (DOT) acc += (double)p[off + (int64_t)r * slab] * (double)v;
+    };
+    if (J == 0) {
+      fin(0, base[0]);
+      fin(N, base[(int64_t)N * slab]);
+    }
     for (int l = J; l >= 1; --l) {
       const int s = N >> l;
       const T c = (T)exp2(0.5 * (double)l);
@@ -129,21 +184,29 @@ __global__ __launch_bounds__(kBlock) void wavelet_kernel(T* __restrict__ X, int 
       for (int m = s; m < N; m += 2 * s) {
         const T yo = base[(int64_t)m * slab];
         const T r_old = base[(int64_t)(m + s) * slab];
-        base[(int64_t)m * slab] =
-            c * ((yo - T(boundary_weight(m - s, N)) * e_old) - T(boundary_weight(m + s, N)) * r_old);
+        const T v = c * ((yo - T(boundary_weight(m - s, N)) * e_old) -
+                         T(boundary_weight(m + s, N)) * r_old);
+        base[(int64_t)m * slab] = v;
+        fin(m, v);
         e_acc += T(0.5) * yo;
         base[(int64_t)(m - s) * slab] = e_acc;
+        if (l == 1) fin(0, e_acc);
         e_old = r_old;
         e_acc = r_old + T(0.5) * yo;
       }
       base[(int64_t)N * slab] = e_acc;
+      if (l == 1) fin(N, e_acc);
     }
+  }
+  if constexpr (DOT) {
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
   }
 }
 
 // ------------------------------------------------------------ reductions
 
-__device__ inline double block_sum(double v) {
+__device__ double block_sum(double v) {
   __shared__ double part[kBlock / 64];
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -511,7 +574,37 @@ hipError_t apply_M(hipStream_t s, const T* x, T* y, int K, int rows) {
 template <typename T>
 hipError_t wavelet(hipStream_t s, T* X, int J, int K, int nrhs, bool synthesis) {
   if (J == 0) return hipSuccess;
-  wavelet_kernel<T><<<dim3(blocks_for(slab_elems(K)), nrhs), kBlock, 0, s>>>(X, J, K, synthesis);
+  const dim3 grid(blocks_for(slab_elems(K)), nrhs);
+  if (synthesis)
+    wavelet_syn_kernel<T, false><<<grid, kBlock, 0, s>>>(X, X, nullptr, nullptr, nullptr, J, K);
+  else
+    wavelet_ana_kernel<T, false><<<grid, kBlock, 0, s>>>(X, nullptr, nullptr, J, K);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t synthesis(hipStream_t s, const T* src, T* dst, int J, int K, int nrhs) {
+  const dim3 grid(blocks_for(slab_elems(K)), nrhs);
+  wavelet_syn_kernel<T, false><<<grid, kBlock, 0, s>>>(src, dst, nullptr, nullptr, nullptr, J, K);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t synthesis_update(hipStream_t s, T* p, const T* z, const double* beta, T* X, int J,
+                            int K, int nrhs) {
+  const dim3 grid(blocks_for(slab_elems(K)), nrhs);
+  wavelet_syn_kernel<T, true><<<grid, kBlock, 0, s>>>(p, X, p, z, beta, J, K);
+  return hipGetLastError();
+}
+
+int analysis_dot_blocks(int K) { return (int)blocks_for(slab_elems(K)); }
+
+template <typename T>
+hipError_t analysis_dot(hipStream_t s, T* X, const T* p, double* partials, double* out, int J,
+                        int K, int nrhs) {
+  const int nblk = analysis_dot_blocks(K);
+  wavelet_ana_kernel<T, true><<<dim3(nblk, nrhs), kBlock, 0, s>>>(X, p, partials, J, K);
+  dot_final_kernel<<<nrhs, kBlock, 0, s>>>(partials, nblk, out);
   return hipGetLastError();
 }
 
@@ -526,7 +619,8 @@ template <typename T>
 hipError_t dot(hipStream_t s, const T* a, const T* b, int64_t n, int nrhs, double* partials,
                double* out) {
   const int nblk = dot_blocks(n);
-  if (n % Vec16<T>::W == 0 && aligned16(a) && aligned16(b))
+  // the vector form helps FP32 (16-byte loads); FP64 streams as fast with 8-byte ones
+  if (sizeof(T) == 4 && n % Vec16<T>::W == 0 && aligned16(a) && aligned16(b))
     dot_partial_vec_kernel<T><<<dim3(nblk, nrhs), kBlock, 0, s>>>(a, b, n, partials);
   else
     dot_partial_kernel<T><<<dim3(nblk, nrhs), kBlock, 0, s>>>(a, b, n, partials);
@@ -550,7 +644,8 @@ hipError_t copy(hipStream_t s, const T* src, T* dst, int64_t count) {
 template <typename T>
 hipError_t update_wr(hipStream_t s, T* w, T* r, const T* p, const T* q, const double* gamma,
                      int64_t n, int nrhs) {
-  if (n % Vec16<T>::W == 0 && aligned16(w) && aligned16(r) && aligned16(p) && aligned16(q)) {
+  if (sizeof(T) == 4 && n % Vec16<T>::W == 0 && aligned16(w) && aligned16(r) && aligned16(p) &&
+      aligned16(q)) {
     const int64_t nv = n / Vec16<T>::W;
     update_wr_vec_kernel<T><<<dim3(blocks_for(nv), nrhs), kBlock, 0, s>>>(
         reinterpret_cast<Vec16<T>*>(w), reinterpret_cast<Vec16<T>*>(r),
@@ -563,7 +658,7 @@ hipError_t update_wr(hipStream_t s, T* w, T* r, const T* p, const T* q, const do
 
 template <typename T>
 hipError_t update_p(hipStream_t s, T* p, const T* z, const double* beta, int64_t n, int nrhs) {
-  if (n % Vec16<T>::W == 0 && aligned16(p) && aligned16(z)) {
+  if (sizeof(T) == 4 && n % Vec16<T>::W == 0 && aligned16(p) && aligned16(z)) {
     const int64_t nv = n / Vec16<T>::W;
     update_p_vec_kernel<T><<<dim3(blocks_for(nv), nrhs), kBlock, 0, s>>>(
         reinterpret_cast<Vec16<T>*>(p), reinterpret_cast<const Vec16<T>*>(z), beta, nv);
@@ -642,6 +737,10 @@ hipError_t fill_level_sigma(hipStream_t s, double* sigma, int J, int nrhs) {
   template hipError_t apply_A<T>(hipStream_t, const T*, T*, int, int);                            \
   template hipError_t apply_M<T>(hipStream_t, const T*, T*, int, int);                            \
   template hipError_t wavelet<T>(hipStream_t, T*, int, int, int, bool);                           \
+  template hipError_t synthesis<T>(hipStream_t, const T*, T*, int, int, int);                     \
+  template hipError_t synthesis_update<T>(hipStream_t, T*, const T*, const double*, T*, int, int, \
+                                          int);                                                  \
+  template hipError_t analysis_dot<T>(hipStream_t, T*, const T*, double*, double*, int, int, int); \
   template hipError_t dot<T>(hipStream_t, const T*, const T*, int64_t, int, double*, double*);    \
   template hipError_t copy<T>(hipStream_t, const T*, T*, int64_t);                                \
   template hipError_t update_wr<T>(hipStream_t, T*, T*, const T*, const T*, const double*,        \

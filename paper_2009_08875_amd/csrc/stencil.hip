@@ -23,6 +23,7 @@ constexpr int kTX = 64, kTY = 16;               // tile
 constexpr int kHX = kTX + 2, kHY = kTY + 2;     // tile with halo
 constexpr int kHalo = kHX * kHY;                // 1188 nodes
 constexpr int kThreads = 256;
+constexpr int kRowsPerThread = kTY * kTX / kThreads;  // consecutive tile rows per thread (4)
 constexpr int kPer = (kHalo + kThreads - 1) / kThreads;  // halo nodes per thread (5)
 constexpr int kChunks[] = {8, 16, 32, 64};      // candidate time rows per workgroup
 
@@ -64,15 +65,17 @@ __device__ __forceinline__ TC<T> time_combo(T xm, T x0, T xp, int i, int N, T in
   return c;
 }
 
+// Spatial stencils on a 3 x 3 register window w[row][column] (row 0 below,
+// column 0 left): M on the "/" mesh (centre 6, the four axis neighbours and
+// the two across the diagonal, times h^2 / 12) and the 5-point A.
 template <typename T>
-__device__ __forceinline__ T Mst(const T* a, int k, T m12) {
-  // k: index of the node in the halo tile; neighbours at +-1 (x), +-kHX (y)
-  return m12 * ((((((T(6) * a[k] + a[k + 1]) + a[k - 1]) + a[k + kHX]) + a[k - kHX]) +
-                 a[k + kHX + 1]) + a[k - kHX - 1]);
+__device__ __forceinline__ T Mw(const T (&w)[3][3], T m12) {
+  return m12 * ((((((T(6) * w[1][1] + w[1][2]) + w[1][0]) + w[2][1]) + w[0][1]) + w[2][2]) +
+                w[0][0]);
 }
 template <typename T>
-__device__ __forceinline__ T Ast(const T* a, int k) {
-  return (((T(4) * a[k] - a[k + 1]) - a[k - 1]) - a[k + kHX]) - a[k - kHX];
+__device__ __forceinline__ T Aw(const T (&w)[3][3]) {
+  return (((T(4) * w[1][1] - w[1][2]) - w[1][0]) - w[2][1]) - w[0][1];
 }
 
 template <typename T, int MODE>
@@ -116,19 +119,31 @@ __global__ __launch_bounds__(kThreads) void row_stencil_kernel(
 
   const int i0 = chunk * chunk_rows;
   const int i1 = min(i0 + chunk_rows, N + 1);
-  T xm[kPer], x0[kPer], xp[kPer];
-  if constexpr (MODE != kCombine) {
+  // time window X_{i-1}, X_i, X_{i+1} of this thread's halo nodes, and the
+  // next row's values loaded one step ahead (combine: z1, z2 of the next row)
+  T xm[kPer], x0[kPer], xp[kPer], nx0[kPer], nx1[kPer];
 #pragma unroll
-    for (int p = 0; p < kPer; ++p) {
+  for (int p = 0; p < kPer; ++p) {
+    if constexpr (MODE != kCombine) {
       xm[p] = i0 > 0 ? ld(in0, i0 - 1, p) : T(0);
       x0[p] = ld(in0, i0, p);
+      nx0[p] = i0 < N ? ld(in0, i0 + 1, p) : T(0);
+    } else {
+      nx0[p] = ld(in0, i0, p);
+      nx1[p] = ld(in1, i0, p);
     }
   }
+  // interior nodes: thread t takes column 1 + t % 64 and the consecutive
+  // rows 1 + 4 (t / 64) .. + 3 of the tile
+  const int lx = 1 + (threadIdx.x & (kTX - 1));
+  const int ly0 = 1 + (threadIdx.x / kTX) * kRowsPerThread;
+  const int gx = gx0 + lx;
   for (int i = i0; i < i1; ++i) {
     if constexpr (MODE != kCombine) {
 #pragma unroll
       for (int p = 0; p < kPer; ++p) {
-        xp[p] = i < N ? ld(in0, i + 1, p) : T(0);
+        xp[p] = nx0[p];
+        nx0[p] = i + 1 < N ? ld(in0, i + 2, p) : T(0);  // in flight during this row
         if (hk[p] < kHalo) {
           const TC<T> c = time_combo(xm[p], x0[p], xp[p], i, N, inv_tau, tau6);
           if constexpr (MODE == kTimePair) {
@@ -146,36 +161,63 @@ __global__ __launch_bounds__(kThreads) void row_stencil_kernel(
 #pragma unroll
       for (int p = 0; p < kPer; ++p) {
         if (hk[p] < kHalo) {
-          s0[hk[p]] = ld(in0, i, p);
-          s1[hk[p]] = ld(in1, i, p);
+          s0[hk[p]] = nx0[p];
+          s1[hk[p]] = nx1[p];
           s2[hk[p]] = (i == 0 && extra && goff[p] >= 0)
                           ? extra[(int64_t)rhs * extra_stride + goff[p]]
                           : T(0);
         }
+        nx0[p] = i + 1 < i1 ? ld(in0, i + 1, p) : T(0);
+        nx1[p] = i + 1 < i1 ? ld(in1, i + 1, p) : T(0);
       }
     }
     __syncthreads();
-    // interior nodes of the tile
-    for (int q = threadIdx.x; q < kTX * kTY; q += kThreads) {
-      const int lx = 1 + q % kTX, ly = 1 + q / kTX;
-      const int gx = gx0 + lx, gy = gy0 + ly;
-      if (gx > n || gy > n) continue;
-      const int k = ly * kHX + lx;
-      const int64_t o = base + (int64_t)i * slab + (int64_t)(gy - 1) * pitch + (gx - 1);
-      if constexpr (MODE == kTimePair) {
-        // y1 = M (A_t X) + A (L^T X),  y2 = A (M_t X) + M (L X)
-        out0[o] = Mst(s0, k, m12) + Ast(s1, k);
-        out1[o] = Ast(s2, k) + Mst(s3, k, m12);
-      } else if constexpr (MODE == kRhsPair) {
-        // G1 = M (L^T g),  G0 = M (M_t g)
-        out0[o] = Mst(s0, k, m12);
-        out1[o] = Mst(s1, k, m12);
-      } else {
-        // M z1 + A z2 (+ M e in row 0)
-        T v = Mst(s0, k, m12) + Ast(s1, k);
-        if (i == 0 && extra) v += Mst(s2, k, m12);
-        out0[o] = v;
+    // spatial stencils, one LDS array at a time: a three-row window of the
+    // array in registers walks up the thread's rows (three new LDS values
+    // per row) and each result is added into the outputs in a fixed order
+    T acc0[kRowsPerThread], acc1[kRowsPerThread];
+    auto pass = [&](const T* arr, bool is_m, T* acc, bool add) {
+      T w[3][3];
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) w[r + 1][c] = arr[(ly0 - 1 + r) * kHX + lx - 1 + c];
+#pragma unroll
+      for (int k = 0; k < kRowsPerThread; ++k) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          w[0][c] = w[1][c];
+          w[1][c] = w[2][c];
+          w[2][c] = arr[(ly0 + k + 1) * kHX + lx - 1 + c];
+        }
+        const T v = is_m ? Mw(w, m12) : Aw(w);
+        acc[k] = add ? acc[k] + v : v;
       }
+      __builtin_amdgcn_sched_barrier(0);  // keep each pass's window live alone
+    };
+    if constexpr (MODE == kTimePair) {
+      // y1 = M (A_t X) + A (L^T X),  y2 = A (M_t X) + M (L X)
+      pass(s0, true, acc0, false);
+      pass(s1, false, acc0, true);
+      pass(s2, false, acc1, false);
+      pass(s3, true, acc1, true);
+    } else if constexpr (MODE == kRhsPair) {
+      // G1 = M (L^T g),  G0 = M (M_t g)
+      pass(s0, true, acc0, false);
+      pass(s1, true, acc1, false);
+    } else {
+      // M z1 + A z2 (+ M e in row 0)
+      pass(s0, true, acc0, false);
+      pass(s1, false, acc0, true);
+      if (i == 0 && extra) pass(s2, true, acc0, true);
+    }
+#pragma unroll
+    for (int k = 0; k < kRowsPerThread; ++k) {
+      const int gy = gy0 + ly0 + k;
+      if (gx > n || gy > n) continue;
+      const int64_t o = base + (int64_t)i * slab + (int64_t)(gy - 1) * pitch + (gx - 1);
+      out0[o] = acc0[k];
+      if constexpr (MODE != kCombine) out1[o] = acc1[k];
     }
     __syncthreads();
     if constexpr (MODE != kCombine) {
