@@ -47,13 +47,16 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-seconds", type=float, default=20.0)
     ap.add_argument("--requests", type=int, default=200, help="serving: open-loop requests")
-    ap.add_argument("--calibration-requests", type=int, default=40,
-                    help="serving: closed-loop requests that measure the saturated rate")
+    ap.add_argument("--calibration-requests", type=int, default=0,
+                    help="serving: closed-loop requests that measure the saturated rate "
+                         "(0: the measured stream itself, all submitted at once)")
     ap.add_argument("--load", type=float, default=0.8,
                     help="serving: arrival rate as a fraction of the saturated rate")
-    ap.add_argument("--budget-gb", type=float, default=120.0, help="serving: device budget")
+    ap.add_argument("--budget-gb", type=float, default=180.0, help="serving: device budget")
     ap.add_argument("--slots", type=int, default=4, help="serving: concurrent groups")
     ap.add_argument("--batch", type=int, default=4, help="serving: requests per group")
+    ap.add_argument("--serve-baseline", action="store_true",
+                    help="serving: also solve the stream one request at a time with plain FP64")
     return ap.parse_args()
 
 
@@ -122,6 +125,33 @@ def measured_traffic(workload, precision, kernel, alg_bytes_per_launch):
     return rec["traffic_bytes_per_launch"]
 
 
+def solo_fp64_sequential(stp, torch, J, K, nrhs, seed, u0kind, tol):
+    """The plain FP64 PCG on the same right-hand sides, one solve at a time
+    (one single-RHS context reused), inputs resident before each timed solve."""
+    import synth
+
+    dev = torch.device("cuda:0")
+    ctx = stp.stp_create(J, K, 1, stp.STP_FP64, stream=torch.cuda.current_stream())
+    total, its = 0.0, 0
+    try:
+        for b in range(-1, nrhs):  # b = -1: untimed warm-up (launch tuning, graph capture)
+            bb = max(b, 0)
+            g = synth.fourier_g_torch(J, K, seed + bb, dev)
+            stp.stp_set_g(ctx, 0, g.reshape(-1))
+            u0 = synth.sine_product(K, 1, 1) if u0kind == "sin" else synth.smooth_u0(K, seed + bb)
+            stp.stp_set_u0(ctx, 0, u0.reshape(-1).copy())
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = stp.stp_solve(ctx, tol)
+            torch.cuda.synchronize()
+            if b >= 0:
+                total += time.perf_counter() - t0
+                its += st[0]["iterations"]
+    finally:
+        stp.stp_destroy(ctx)
+    return {"time_s": round(total, 4), "solves": nrhs, "iterations_sum": its}
+
+
 def cpu_baseline(seconds_budget):
     """The oracle (NumPy FP64, unmodified) on a bounded sample of the workload:
     PCG on the same mesh (h = 2^-9) with 2^1 + 1 time rows, seeded Fourier
@@ -166,10 +196,11 @@ def cpu_baseline(seconds_budget):
     }
 
 
-def serve_stream(stp, torch, server, reqs, prec, rate):
-    """Submit `reqs` (all at once when rate is None, else at Poisson arrival
-    times of that rate), wait for all; returns per-request results and the
-    span from the first submission to the last completion."""
+def serve_stream(stp, torch, server, reqs, prec, rate, window=16):
+    """Submit `reqs` at Poisson arrival times of the given rate, or, when rate
+    is None, as a closed loop that keeps `window` requests submitted and
+    unfinished; wait for all.  Returns per-request results and the span from
+    the first submission to the last completion."""
     import synth
 
     dev = torch.device("cuda:0")
@@ -183,7 +214,7 @@ def serve_stream(stp, torch, server, reqs, prec, rate):
     t0 = time.perf_counter()
     while i < len(reqs) or inflight:
         now = time.perf_counter() - t0
-        while i < len(reqs) and now >= arrivals[i]:
+        while i < len(reqs) and now >= arrivals[i] and (rate is not None or len(inflight) < window):
             r = reqs[i]
             g = synth.fourier_g_torch(r["J"], r["K"], r["seed"], dev).reshape(-1)
             u0 = torch.as_tensor(synth.smooth_u0(r["K"], r["seed"]).reshape(-1), device=dev)
@@ -207,6 +238,46 @@ def serve_stream(stp, torch, server, reqs, prec, rate):
     return results, time.perf_counter() - t0
 
 
+def plain_sequential(stp, torch, reqs, _unused=None):
+    """The request stream solved one request at a time by plain FP64 PCG
+    (a context per shape, reused), each request's inputs resident before its
+    timed solve."""
+    import synth
+
+    dev = torch.device("cuda:0")
+    ctxs, total = {}, 0.0
+    try:
+        for r in reqs:
+            key = (r["J"], r["K"])
+            if key not in ctxs:
+                ctxs[key] = stp.stp_create(r["J"], r["K"], 1, stp.STP_FP64,
+                                           stream=torch.cuda.current_stream())
+                warm = True
+            else:
+                warm = False
+            ctx = ctxs[key]
+            g = synth.fourier_g_torch(r["J"], r["K"], r["seed"], dev).reshape(-1)
+            stp.stp_set_g(ctx, 0, g)
+            stp.stp_set_u0(ctx, 0, synth.smooth_u0(r["K"], r["seed"]).reshape(-1).copy())
+            torch.cuda.synchronize()
+            if warm:  # untimed first solve of a shape: launch tuning and graph capture
+                stp.stp_solve(ctx, r["tol"])
+                torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            stp.stp_solve(ctx, r["tol"])
+            torch.cuda.synchronize()
+            total += time.perf_counter() - t0
+            del g
+            if len(ctxs) > 6:  # keep device memory bounded
+                for k in list(ctxs)[:-1]:
+                    stp.stp_destroy(ctxs.pop(k))
+    finally:
+        for c in ctxs.values():
+            stp.stp_destroy(c)
+    return {"time_s": round(total, 3), "solves": len(reqs),
+            "solves_per_s": round(len(reqs) / total, 3)}
+
+
 def run_serving(args, stp, torch):
     import numpy as np
 
@@ -214,8 +285,9 @@ def run_serving(args, stp, torch):
 
     prec = stp.STP_MIXED if args.precision == "mixed" else stp.STP_FP64
     warm = synth.serving_stream(12, seed=12343)
-    cal = synth.serving_stream(args.calibration_requests, seed=12344)
     reqs = synth.serving_stream(args.requests, seed=12345)
+    cal = reqs if args.calibration_requests <= 0 else synth.serving_stream(
+        args.calibration_requests, seed=12344)
     server = stp.stp_server_create(int(args.budget_gb * 1e9), max_slots=args.slots,
                                    max_batch=args.batch)
     try:
@@ -242,6 +314,7 @@ def run_serving(args, stp, torch):
         "requests": len(res),
         "rate_per_s": round(rate, 3),
         "saturated_solves_per_s": round(saturated, 3),
+        "closed_loop_span_s": round(span_cal, 3),
         "solves_per_s": round(len(res) / span, 3),
         "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
         "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
@@ -252,6 +325,10 @@ def run_serving(args, stp, torch):
         "statuses": statuses,
         "failed": len(res) - len(ok),
     }
+    if args.serve_baseline:
+        serving["plain_fp64_sequential"] = plain_sequential(stp, torch, reqs)
+        print(f"# plain FP64, one request at a time: {serving['plain_fp64_sequential']}",
+              file=sys.stderr, flush=True)
     line = {
         "metric": METRIC,
         "value": work / span,
@@ -350,6 +427,12 @@ def main():
         }
         print(f"# compare: {compare}", file=sys.stderr, flush=True)
 
+    solo = None
+    if nrhs > 1 and not args.no_compare:
+        solo = solo_fp64_sequential(stp, torch, J, K, nrhs, seed, u0kind, args.tol)
+        solo["speedup_of_batched"] = round(solo["time_s"] / t_step, 3)
+        print(f"# solo FP64, one right-hand side at a time: {solo}", file=sys.stderr, flush=True)
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_sample_seconds)
 
     line = {
@@ -373,6 +456,8 @@ def main():
         "cpu_baseline": cpu,
         "compare": compare,
     }
+    if solo is not None:
+        line["solo_fp64_sequential"] = solo
     print(json.dumps(line), flush=True)
 
 

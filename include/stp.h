@@ -158,7 +158,8 @@ stp_status stp_profile_read(stp_ctx* ctx, int kernel, stp_kernel_stat* out);
  * admits it together with up to max_batch - 1 waiting requests of the same
  * (J, K, precision) whose tolerance is within a factor of 10 of its own, as
  * the right-hand sides of one batched context (groups of 1, 2, 4, ...
- * requests).  Running groups advance independently, one PCG
+ * requests; only problems whose single context is at most 2 GiB are grouped:
+ * a larger one fills the device alone).  Running groups advance independently, one PCG
  * iteration or refinement step at a time, on separate streams, so requests
  * admitted while others run overlap with them on the device.  Every
  * right-hand side of a group computes exactly its solo solve (its own

@@ -4,8 +4,9 @@
 // worker thread.  Requests wait in arrival order.  Whenever a slot is free and
 // the head request's context fits in the budget, the worker admits it,
 // together with up to max_batch - 1 waiting requests of the same (J, K,
-// precision) and a similar tolerance: they become the right-hand sides of
-// one batched context, so every operator of the group is one launch.  Admitted groups run at the
+// precision) and a similar tolerance, if the problem is small: they become
+// the right-hand sides of one batched context, so every operator of the
+// group is one launch.  Admitted groups run at the
 // same time on different streams: the worker advances every group by one
 // unit of device work (one PCG iteration, or a refinement step) as soon as
 // its previous unit has completed, so work of groups admitted at different
@@ -64,6 +65,9 @@ struct Cached {
   size_t bytes;
   int J, K, prec, nrhs;
 };
+
+// Requests whose single context is larger than this are never grouped.
+constexpr size_t kGroupMaxBytes = size_t(2) << 30;
 
 int pow2_floor(int n) {
   int p = 1;
@@ -183,9 +187,14 @@ void admit(stp_server* s) {
       const stp_request& h = s->waiting.front()->req;
       // requests of the same shape and a tolerance within a factor of 10 of
       // the head's (so the group's right-hand sides need similar iteration
-      // counts) join the head request, up to max_batch of them
+      // counts) join the head request, up to max_batch of them -- for small
+      // problems only, whose launches are too short to fill the device; a
+      // large one fills it alone and grouping would only hold device memory
       std::vector<size_t> idx{0};
-      for (size_t i = 1; i < s->waiting.size() && (int)idx.size() < s->max_batch; ++i) {
+      size_t one = 0;
+      const bool small = stp_footprint(h.J, h.K, 1, h.precision, &one) == STP_OK &&
+                         one <= kGroupMaxBytes;
+      for (size_t i = 1; small && i < s->waiting.size() && (int)idx.size() < s->max_batch; ++i) {
         const stp_request& q = s->waiting[i]->req;
         if (q.J == h.J && q.K == h.K && q.precision == h.precision &&
             q.rel_tol <= 10.0 * h.rel_tol && h.rel_tol <= 10.0 * q.rel_tol)
