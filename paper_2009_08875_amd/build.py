@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libstp.so")
 
-SOURCES = ["kernels.hip", "mg_stream.hip", "stencil.hip", "tune.cpp", "api.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "mg_stream.hip", "mg_coarse.hip", "stencil.hip", "tune.cpp", "api.cpp",
+           "server.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -242,12 +242,12 @@ stp_status mg_apply(stp_ctx* c, MgScratch<T>& mg, const T* b, T* x, int64_t rows
     const T* bb = b + r0 * slab;
     T* xx = x + r0 * slab;
     const double* sg = sigma ? sigma + r0 : nullptr;
-    if (K == 1) {
-      if (write_Ax) {
-        HIP_TRY(mg_coarsest<T>(c->stream, bb, mg.xb[1], nr, a, sg));
-        HIP_TRY(apply_A<T>(c->stream, mg.xb[1], xx, K, nr));
-      } else {
-        HIP_TRY(mg_coarsest<T>(c->stream, bb, xx, nr, a, sg));
+    if (K <= kCoarseLevels) {
+      // the whole cycle fits one workgroup per row (all levels in LDS)
+      for (int cyc = 0; cyc < c->opt.vcycles; ++cyc) {
+        const bool last = cyc == c->opt.vcycles - 1;
+        HIP_TRY(mg_coarse_cycle<T>(c->stream, cyc == 0 ? nullptr : xx, bb, xx, K, nr, a, sg,
+                                   write_Ax && last));
       }
       continue;
     }
@@ -263,10 +263,12 @@ stp_status mg_apply(stp_ctx* c, MgScratch<T>& mg, const T* b, T* x, int64_t rows
       STP_TRY(timed_launch(c, STP_KERNEL_MG_PRE, pre_bytes, [&] {
         return mg_pre_stream<T>(c->stream, xin, bb, mg.xb[K], mg.b[K - 1], K, nr, a, sg);
       }));
-      for (int l = K - 1; l >= 2; --l)
+      for (int l = K - 1; l > kCoarseLevels; --l)
         HIP_TRY(mg_pre_stream<T>(c->stream, nullptr, mg.b[l], mg.xb[l], mg.b[l - 1], l, nr, a, sg));
-      HIP_TRY(mg_coarsest<T>(c->stream, mg.b[1], mg.xa[1], nr, a, sg));
-      for (int l = 2; l <= K - 1; ++l)
+      // levels kCoarseLevels .. 1 in one launch, from zero
+      HIP_TRY(mg_coarse_cycle<T>(c->stream, nullptr, mg.b[kCoarseLevels], mg.xa[kCoarseLevels],
+                                 kCoarseLevels, nr, a, sg, false));
+      for (int l = kCoarseLevels + 1; l <= K - 1; ++l)
         HIP_TRY(mg_post_stream<T>(c->stream, mg.xb[l], mg.b[l], mg.xa[l - 1], mg.xa[l], l, nr, a, sg,
                                   false));
       const double post_bytes = sizeof(T) * (3.0 * nodes + cnodes);

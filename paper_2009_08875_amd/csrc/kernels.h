@@ -31,9 +31,13 @@ template <typename T>
 hipError_t mg_post_stream(hipStream_t s, const T* xin, const T* b, const T* ec, T* xout, int l,
                           int rows, double a, const double* sigma, bool write_Ax);
 
-// Exact solve on the one-node grid (level 1): x = b / (4a + sigma/8).
+// One V-cycle on levels L..1 (L <= kCoarseLevels) per row, each row in one
+// workgroup with all levels in LDS (mg_coarse.hip): xout = V(L, b, xin) (xin
+// NULL: from zero), or A_x applied to it when write_Ax.  xout may alias xin.
+constexpr int kCoarseLevels = 5;
 template <typename T>
-hipError_t mg_coarsest(hipStream_t s, const T* b, T* x, int rows, double a, const double* sigma);
+hipError_t mg_coarse_cycle(hipStream_t s, const T* xin, const T* b, T* xout, int L, int rows,
+                           double a, const double* sigma, bool write_Ax);
 
 // ---- space-time stencils (Lemma 4.2 and Lemma 4.1, applied row-wise through
 // the Kronecker identity, eq. (15) of Section 5.2).  X has nrhs * (2^J+1) slabs

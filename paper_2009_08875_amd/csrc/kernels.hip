@@ -23,20 +23,6 @@ inline unsigned blocks_for(int64_t count, int per_block = kBlock) {
   return (unsigned)((count + per_block - 1) / per_block);
 }
 
-// ---------------------------------------------------------------- multigrid
-
-// Exact solve on the one-node grid (level 1, h = 1/2).
-template <typename T>
-__global__ void mg_coarsest_kernel(const T* __restrict__ b, T* __restrict__ x, int rows, double a,
-                                   const double* __restrict__ sigma) {
-  const int row = blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= rows) return;
-  const double sg = sigma ? sigma[row] : 0.0;
-  const double c0 = 4.0 * a + sg / 8.0;  // h = 1/2: sigma h^2 / 2 = sigma / 8
-  const int64_t slab = slab_elems(1);
-  x[(int64_t)row * slab] = (T)((double)b[(int64_t)row * slab] / c0);
-}
-
 // ------------------------------------------------------------ row stencils
 
 __device__ inline bool node_of(int64_t idx, int K, int& gx, int& gy) {
@@ -554,12 +540,6 @@ __global__ void fill_level_sigma_kernel(double* sigma, int J, int nrhs) {
 // ================================================================ launchers
 
 template <typename T>
-hipError_t mg_coarsest(hipStream_t s, const T* b, T* x, int rows, double a, const double* sigma) {
-  mg_coarsest_kernel<T><<<blocks_for(rows), kBlock, 0, s>>>(b, x, rows, a, sigma);
-  return hipGetLastError();
-}
-
-template <typename T>
 hipError_t apply_A(hipStream_t s, const T* x, T* y, int K, int rows) {
   apply_AM_kernel<T, true><<<dim3(blocks_for(slab_elems(K)), rows), kBlock, 0, s>>>(x, y, K);
   return hipGetLastError();
@@ -733,7 +713,6 @@ hipError_t fill_level_sigma(hipStream_t s, double* sigma, int J, int nrhs) {
 
 // ---------------------------------------------------------- instantiations
 #define STP_INSTANTIATE(T)                                                                        \
-  template hipError_t mg_coarsest<T>(hipStream_t, const T*, T*, int, double, const double*);      \
   template hipError_t apply_A<T>(hipStream_t, const T*, T*, int, int);                            \
   template hipError_t apply_M<T>(hipStream_t, const T*, T*, int, int);                            \
   template hipError_t wavelet<T>(hipStream_t, T*, int, int, int, bool);                           \
