@@ -15,21 +15,23 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
+#include "tune.h"
 
 namespace stp {
 
 namespace {
 
-constexpr int kThreads = 256;
 
 struct LevelCoef {
   double c0, c1, c2;  // centre, axis neighbours, the two "/" diagonal neighbours
+  double inv_c0;
 };
 
 __device__ __forceinline__ LevelCoef level_coef(double a, double sigma, int l) {
   const double h = 1.0 / (double)(1 << l);
   const double m = h * h / 12.0;
-  return {4.0 * a + 6.0 * m * sigma, -a + m * sigma, m * sigma};
+  const double c0 = 4.0 * a + 6.0 * m * sigma;
+  return {c0, -a + m * sigma, m * sigma, 1.0 / c0};
 }
 
 // Compact n x n arrays in LDS; node (i, j), 1-based, at (j - 1) n + (i - 1).
@@ -41,10 +43,10 @@ __device__ __forceinline__ T at(const T* v, int n, int i, int j) {
 // One colour of Gauss-Seidel: every node (i, j) with (i + j) mod 3 == colour
 // gets (b - sum_nb C_nb x_nb) / C_centre from the current neighbours (no two
 // nodes of one colour are coupled, so the update is in place).
-template <typename T>
+template <int NT, typename T>
 __device__ void relax(T* x, const T* b, int n, int colour, const LevelCoef& cf) {
   const int m = (n + 2) / 3;  // nodes of one colour per grid line, at most
-  for (int k = threadIdx.x; k < n * m; k += kThreads) {
+  for (int k = threadIdx.x; k < n * m; k += NT) {
     const int j = k / m + 1;
     int i = ((colour - j) % 3 + 3) % 3;
     if (i == 0) i = 3;
@@ -53,22 +55,23 @@ __device__ void relax(T* x, const T* b, int n, int colour, const LevelCoef& cf) 
     const T off = T(cf.c1) * (((at(x, n, i + 1, j) + at(x, n, i - 1, j)) + at(x, n, i, j + 1)) +
                               at(x, n, i, j - 1)) +
                   T(cf.c2) * (at(x, n, i + 1, j + 1) + at(x, n, i - 1, j - 1));
-    x[(j - 1) * n + (i - 1)] = (b[(j - 1) * n + (i - 1)] - off) / T(cf.c0);
+    x[(j - 1) * n + (i - 1)] = (b[(j - 1) * n + (i - 1)] - off) * T(cf.inv_c0);
   }
 }
 
-template <typename T>
+template <int NT, typename T>
 __device__ void sweeps(T* x, const T* b, int n, const LevelCoef& cf, bool forward) {
   for (int s = 0; s < 3; ++s) {
     for (int c = 0; c < 3; ++c) {
-      relax(x, b, n, forward ? c : 2 - c, cf);
+      relax<NT>(x, b, n, forward ? c : 2 - c, cf);
       __syncthreads();
     }
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void mg_coarse_kernel(const T* xin, const T* b, T* xout,
+// NT threads per workgroup (one time row each); the result does not depend on NT.
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void mg_coarse_kernel(const T* xin, const T* b, T* xout,
                                                              int L, double a,
                                                              const double* __restrict__ sigma,
                                                              int write_Ax) {
@@ -87,7 +90,7 @@ __global__ __launch_bounds__(kThreads) void mg_coarse_kernel(const T* xin, const
   const double sg = sigma ? sigma[row] : 0.0;
   const int n = nl(L), pitch = line_pitch(L);
   const int64_t base = (int64_t)row * slab_elems(L);
-  for (int k = threadIdx.x; k < n * n; k += kThreads) {
+  for (int k = threadIdx.x; k < n * n; k += NT) {
     const int64_t g = base + (int64_t)(k / n) * pitch + (k % n);
     sh[off_b(L) + k] = b[g];
     sh[off_x(L) + k] = xin ? xin[g] : T(0);
@@ -100,11 +103,11 @@ __global__ __launch_bounds__(kThreads) void mg_coarse_kernel(const T* xin, const
     const T* bl = sh + off_b(l);
     const int nn = nl(l);
     if (l < L) {
-      for (int k = threadIdx.x; k < nn * nn; k += kThreads) x[k] = T(0);
+      for (int k = threadIdx.x; k < nn * nn; k += NT) x[k] = T(0);
       __syncthreads();
     }
-    sweeps(x, bl, nn, cf, true);
-    for (int k = threadIdx.x; k < nn * nn; k += kThreads) {
+    sweeps<NT>(x, bl, nn, cf, true);
+    for (int k = threadIdx.x; k < nn * nn; k += NT) {
       const int i = k % nn + 1, j = k / nn + 1;
       const T cx = T(cf.c0) * x[k] +
                    T(cf.c1) * (((at(x, nn, i + 1, j) + at(x, nn, i - 1, j)) + at(x, nn, i, j + 1)) +
@@ -115,7 +118,7 @@ __global__ __launch_bounds__(kThreads) void mg_coarse_kernel(const T* xin, const
     __syncthreads();
     T* bc = sh + off_b(l - 1);
     const int mc = nl(l - 1);
-    for (int k = threadIdx.x; k < mc * mc; k += kThreads) {
+    for (int k = threadIdx.x; k < mc * mc; k += NT) {
       const int I = k % mc + 1, J = k / mc + 1;
       const int i = 2 * I, j = 2 * J;
       const T half = ((((at(r, nn, i + 1, j) + at(r, nn, i - 1, j)) + at(r, nn, i, j + 1)) +
@@ -127,7 +130,7 @@ __global__ __launch_bounds__(kThreads) void mg_coarse_kernel(const T* xin, const
     __syncthreads();
   }
   // the one-node grid (h = 1/2)
-  if (threadIdx.x == 0) sh[off_x(1)] = sh[off_b(1)] / T(level_coef(a, sg, 1).c0);
+  if (threadIdx.x == 0) sh[off_x(1)] = sh[off_b(1)] * T(level_coef(a, sg, 1).inv_c0);
   __syncthreads();
   // up: prolongate the correction, smooth backwards
   for (int l = 2; l <= L; ++l) {
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(kThreads) void mg_coarse_kernel(const T* xin, const
     T* x = sh + off_x(l);
     const T* e = sh + off_x(l - 1);
     const int nn = nl(l), mc = nl(l - 1);
-    for (int k = threadIdx.x; k < nn * nn; k += kThreads) {
+    for (int k = threadIdx.x; k < nn * nn; k += NT) {
       const int i = k % nn + 1, j = k / nn + 1;
       T p;
       if (!(i & 1) && !(j & 1)) {
@@ -150,10 +153,10 @@ __global__ __launch_bounds__(kThreads) void mg_coarse_kernel(const T* xin, const
       x[k] += p;
     }
     __syncthreads();
-    sweeps(x, sh + off_b(l), nn, cf, false);
+    sweeps<NT>(x, sh + off_b(l), nn, cf, false);
   }
   const T* x = sh + off_x(L);
-  for (int k = threadIdx.x; k < n * n; k += kThreads) {
+  for (int k = threadIdx.x; k < n * n; k += NT) {
     const int i = k % n + 1, j = k / n + 1;
     T v = x[k];
     if (write_Ax)
@@ -177,8 +180,22 @@ hipError_t mg_coarse_cycle(hipStream_t s, const T* xin, const T* b, T* xout, int
                            double a, const double* sigma, bool write_Ax) {
   if (L < 1 || L > kCoarseLevels) return hipErrorInvalidValue;
   const size_t lds = mg_coarse_lds_bytes(L, sizeof(T));
-  mg_coarse_kernel<T><<<rows, kThreads, lds, s>>>(xin, b, xout, L, a, sigma, write_Ax ? 1 : 0);
-  return hipGetLastError();
+  // workgroups of 2, 4 or 8 waves per time row (tuned per level and row count)
+  auto go = [&](int c) -> hipError_t {
+    const int wa = write_Ax ? 1 : 0;
+    if (c == 0)
+      mg_coarse_kernel<T, 256><<<rows, 256, lds, s>>>(xin, b, xout, L, a, sigma, wa);
+    else if (c == 1)
+      mg_coarse_kernel<T, 128><<<rows, 128, lds, s>>>(xin, b, xout, L, a, sigma, wa);
+    else
+      mg_coarse_kernel<T, 512><<<rows, 512, lds, s>>>(xin, b, xout, L, a, sigma, wa);
+    return hipGetLastError();
+  };
+  const uint64_t key = tune_key(3, sizeof(T), (uint64_t)L, (uint64_t)rows);
+  // a cycle that starts from its own output cannot be repeated for timing:
+  // it takes the choice made for the same shape from zero
+  if (xin != nullptr && xin == xout) return go(tuned_choice(key, 0));
+  return go(tuned(key, 3, 0, s, go));
 }
 
 template hipError_t mg_coarse_cycle<double>(hipStream_t, const double*, const double*, double*,

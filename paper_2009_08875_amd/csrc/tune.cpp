@@ -68,4 +68,10 @@ int tuned(uint64_t key, int candidates, int fallback, hipStream_t stream,
   return best;
 }
 
+int tuned_choice(uint64_t key, int fallback) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_choice.find(key);
+  return it == g_choice.end() ? fallback : it->second;
+}
+
 }  // namespace stp

@@ -22,6 +22,10 @@ namespace stp {
 int tuned(uint64_t key, int candidates, int fallback, hipStream_t stream,
           const std::function<hipError_t(int)>& launch);
 
+// The choice remembered for key, or fallback; never runs anything (for
+// launches that update their output in place and so cannot be repeated).
+int tuned_choice(uint64_t key, int fallback);
+
 inline uint64_t tune_key(uint64_t a, uint64_t b, uint64_t c, uint64_t d) {
   return (a << 56) ^ (b << 40) ^ (c << 24) ^ d;
 }
