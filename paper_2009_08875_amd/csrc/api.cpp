@@ -35,7 +35,7 @@ stp_options resolve(const stp_options* o) {
   if (r.vcycles <= 0) r.vcycles = 2;
   if (r.sweeps <= 0) r.sweeps = 3;
   if (r.maxit <= 0) r.maxit = 200;
-  if (r.inner_tol <= 0.0) r.inner_tol = 1e-4;
+  if (r.inner_tol <= 0.0) r.inner_tol = 3e-3;
   if (r.max_outer <= 0) r.max_outer = 20;
   if (r.graph > 0) r.graph = 1;
   return r;
