@@ -64,7 +64,8 @@ typedef struct {
   int vcycles;       /* V-cycles per multigrid application; 0 -> 2 */
   int sweeps;        /* Gauss-Seidel steps before and after the coarse grid; 0 -> 3 */
   int maxit;         /* PCG iteration limit (inner limit in STP_MIXED); 0 -> 200 */
-  double inner_tol;  /* STP_MIXED: relative reduction per inner solve; 0 -> 3e-3 */
+  double inner_tol;  /* STP_MIXED: relative reduction per inner solve; 0 -> by mesh:
+                        1e-4 for K <= 7, 1e-3 for K = 8, 3e-3 for K >= 9 */
   int max_outer;     /* STP_MIXED: refinement-step limit; 0 -> 20 */
   int graph;         /* replay each PCG iteration from a captured HIP graph:
                         0 (default) or 1 -> yes (not while profiling), -1 -> no */
