@@ -327,3 +327,63 @@ def test_graph_replay_equals_eager(stp, prec):
     finally:
         stp.stp_destroy(eager)
         stp.stp_destroy(graph)
+
+
+def test_mixed_edge_cases(stp):
+    """The device-side control of the mixed form: zero data stops at once
+    with u = 0; a single outer step with one inner iteration reports
+    NOT_CONVERGED with a finite iterate; non-finite data reports breakdown."""
+    say("mixed form: zero data, limits, NaN")
+    J, K = 3, 4
+    n = 2 ** K - 1
+    u, its, status, st = _gpu_solve(stp, J, K, None, np.zeros((n, n)), 1e-8, stp.STP_MIXED)
+    assert status == stp.STP_OK and its == 0 and not np.any(u)
+
+    ctx = stp.stp_create(J, K, 1, stp.STP_MIXED, {"maxit": 1, "max_outer": 1})
+    try:
+        stp.stp_set_u0(ctx, 0, flat(sin_u0(K)))
+        status, st = stp.stp_solve(ctx, 1e-10)
+        u = np.zeros((2 ** J + 1) * n * n)
+        stp.stp_get_solution(ctx, 0, u)
+    finally:
+        stp.stp_destroy(ctx)
+    assert status == stp.STP_NOT_CONVERGED and st[0]["iterations"] == 1
+    assert st[0]["outer_iterations"] == 1
+    assert np.all(np.isfinite(u)) and np.any(u)
+
+    g = np.zeros((2 ** J + 1, n, n))
+    g[3, 5, 5] = np.inf
+    ctx = stp.stp_create(J, K, 1, stp.STP_MIXED)
+    try:
+        stp.stp_set_g(ctx, 0, flat(g))
+        stp.stp_set_u0(ctx, 0, flat(sin_u0(K)))
+        with pytest.raises(stp.StpError) as e:
+            stp.stp_solve(ctx, 1e-8)
+        assert e.value.status == stp.STP_E_BREAKDOWN
+    finally:
+        stp.stp_destroy(ctx)
+
+
+def test_context_is_reusable_after_a_failed_solve(stp):
+    """A breakdown leaves the context usable: new data solve normally and
+    give the same result as a fresh context."""
+    say("context reuse after breakdown")
+    J, K = 2, 3
+    g_bad = np.zeros((5, 7, 7))
+    g_bad[1, 2, 2] = np.nan
+    g, u0 = synth.fourier_g(J, K, 31), synth.smooth_u0(K, 31)
+    ctx = stp.stp_create(J, K, 1, stp.STP_FP64)
+    try:
+        stp.stp_set_g(ctx, 0, flat(g_bad))
+        stp.stp_set_u0(ctx, 0, flat(u0))
+        with pytest.raises(stp.StpError):
+            stp.stp_solve(ctx, 1e-8)
+        stp.stp_set_g(ctx, 0, flat(g))
+        status, st = stp.stp_solve(ctx, 1e-8)
+        u = np.zeros(g.size)
+        stp.stp_get_solution(ctx, 0, u)
+    finally:
+        stp.stp_destroy(ctx)
+    u_fresh, its, s2, _ = _gpu_solve(stp, J, K, g, u0, 1e-8, stp.STP_FP64)
+    assert status == stp.STP_OK and st[0]["iterations"] == its
+    assert np.array_equal(u, u_fresh.ravel())
