@@ -114,6 +114,7 @@ __device__ __forceinline__ int64_t uniform(int64_t v) {
 // needs a branch or a mask.
 using Rsrc = __amdgpu_buffer_rsrc_t;
 constexpr int kRsrcWord3 = 0x00020000;  // 32-bit data format, raw (untyped) access
+constexpr int kCachePolicyNT = 2;       // non-temporal (streaming) store
 
 __device__ __forceinline__ Rsrc rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRsrcWord3);
@@ -125,13 +126,16 @@ __device__ __forceinline__ T buf_load(Rsrc r, int voff) {
   else
     return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
 }
+// Stores carry the non-temporal cache policy: a written row is not read again
+// by this kernel, and streaming it out keeps the L2 for the rows in flight.
 template <typename T>
 __device__ __forceinline__ void buf_store(T v, Rsrc r, int voff) {
   if constexpr (sizeof(T) == 8) {
     using V2 = unsigned int __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, voff, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, voff, 0, kCachePolicyNT);
   } else {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, 0,
+                                         kCachePolicyNT);
   }
 }
 
@@ -224,12 +228,13 @@ struct Args {
 };
 
 // One Gauss-Seidel update of the column with in-lane index K in the row held
-// in slot SR (neighbour rows in slots SN above, SS below).  Columns outside
+// in slot SR (neighbour rows in slots SN above, SS below); t is its scaled
+// right-hand side b / c0.  Columns outside
 // the grid have cinv = q1 = q2 = 0 and b = 0, so they stay exactly zero.
 // FWD: the value written by the previous phase is the north-east neighbour
 // (it only matters with the mass term, DIAG); backward: the north neighbour.
 template <typename T, bool FWD, bool DIAG, int K, int SR, int SN, int SS>
-__device__ __forceinline__ void relax(State<T>& st, const Args<T>& A) {
+__device__ __forceinline__ void relax(State<T>& st, const Args<T>& A, T t) {
   T xe, xw, xne = T(0), xsw = T(0);
   if constexpr (K < 2) {
     xe = st.x[SR][K + 1];
@@ -247,7 +252,6 @@ __device__ __forceinline__ void relax(State<T>& st, const Args<T>& A) {
   }
   const T xn = st.x[SN][K], xs = st.x[SS][K];
   const T m1 = -A.q1[K], m2 = -A.q2[K];
-  T t = bget<T, SR, K>(st);
   if constexpr (FWD) {
     // the north-east neighbour was written by the previous phase: it goes last
     t = fma(m1, xe, t);
@@ -344,6 +348,16 @@ template <typename T, bool PRE, bool XIN, bool DIAG, bool WRITE_A, bool CHK, int
 __device__ __forceinline__ void step(State<T>& st, const Args<T>& A, int s0) {
   const int s = s0 + U;
   const int n = A.n;
+  // ---- the right-hand sides of the nine rows this step relaxes (rows s - 8
+  // .. s, all in the LDS window already) are read first, so that their LDS
+  // latency overlaps the assembly of row s + 1 instead of stalling each phase
+  T bv[kPhases];
+  static_for<0, kPhases>([&](auto PP) {
+    constexpr int P = decltype(PP)::value;
+    constexpr int colour = PRE ? (P % 3) : (2 - P % 3);
+    bv[P] = bget<T, mod(U - P, kWin), mod(colour - 1 - (U - P), 3)>(st);
+  });
+  __builtin_amdgcn_sched_barrier(0);
   // ---- assemble row s + 1 from its prefetched values
   {
     constexpr int SL = mod(U + 1, kWin);
@@ -424,7 +438,7 @@ __device__ __forceinline__ void step(State<T>& st, const Args<T>& A, int s0) {
     constexpr int SN = mod(U - P + 1, kWin);
     constexpr int SS = mod(U - P - 1, kWin);
     const int r = s - P;
-    if (!CHK || (r >= 1 && r <= n)) relax<T, PRE, DIAG, K, SR, SN, SS>(st, A);
+    if (!CHK || (r >= 1 && r <= n)) relax<T, PRE, DIAG, K, SR, SN, SS>(st, A, bv[P]);
   });
   if constexpr (!WRITE_A) {
     // ---- row s - 8 has had all nine phases: write it (coalesced, via LDS;
