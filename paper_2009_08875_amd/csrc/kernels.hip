@@ -6,6 +6,7 @@
 // the space-time stencils) live in mg_stream.hip and stencil.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -186,6 +187,188 @@ __global__ __launch_bounds__(kBlock) void wavelet_ana_kernel(T* __restrict__ X,
   }
   if constexpr (DOT) {
     acc = block_sum(acc);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
+  }
+}
+
+// ------------------------------------------------- wavelet, whole columns in LDS
+//
+// For FP64 time axes of at most 2^kLdsJMax intervals a workgroup holds whole
+// columns: lds_cols<T>() adjacent slab columns (one 128-byte line per row)
+// for all N + 1 rows.  Each row is read from HBM once and written once, and
+// every level runs in LDS, where the column kernels above re-read and
+// re-write rows level by level.  Within a level the odd rows of a column are
+// cut into runs of consecutive odd rows, one run per thread; a run is
+// processed left to right exactly as the column kernels process a whole
+// level (the same operations in the same order, so the results are the
+// same), with the two values it shares with the neighbouring runs -- the
+// odd row just left of it and the even row just right of it -- read before
+// the level starts.
+constexpr int kLdsJMax = 10;
+constexpr int kLdsThreads = 1024;
+constexpr int kLdsGrid = 2048;  // workgroups per right-hand side, at most
+template <typename T>
+constexpr int lds_cols() {
+  return 128 / (int)sizeof(T);
+}
+
+template <int NT>
+__device__ double block_sum_n(double v) {
+  __shared__ double part[NT / 64];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) part[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NT / 64; ++k) t += part[k];
+  }
+  __syncthreads();
+  return t;
+}
+
+// Runs of one level: thread g of a column takes odd rows (2k + 1) s for k in
+// [k0, k1) of the `items` odd rows.
+struct LevelRun {
+  int k0, k1;
+};
+__device__ __forceinline__ LevelRun level_run(int items, int g, int threads_per_col) {
+  const int per = (items + threads_per_col - 1) / threads_per_col;
+  const int k0 = min(g * per, items);
+  return {k0, min(k0 + per, items)};
+}
+
+template <typename T, bool UPD, int JMAX>
+__global__ __launch_bounds__(kLdsThreads) void wavelet_syn_lds_kernel(const T* src, T* dst, T* p,
+                                                                      const T* __restrict__ z,
+                                                                      const double* __restrict__ beta,
+                                                                      int J, int K) {
+  constexpr int C = lds_cols<T>();
+  constexpr int RG = kLdsThreads / C;  // threads per column
+  __shared__ T sh[((1 << JMAX) + 1) * C];
+  const int64_t slab = slab_elems(K);
+  const int N = 1 << J;
+  const int c = threadIdx.x % C, g = threadIdx.x / C;
+  const double bt = UPD ? beta[blockIdx.y] : 0.0;
+  const int64_t groups = (slab + C - 1) / C;
+  for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+    const int64_t col = grp * C + c;
+    const bool ok = col < slab;
+    const int64_t off = (int64_t)blockIdx.y * (N + 1) * slab + col;
+    // every row's coefficient (with UPD: p = z + beta p, written back)
+#pragma unroll 4
+    for (int r = g; r <= N; r += RG) {
+      T v = T(0);
+      if (ok) {
+        const int64_t o = off + (int64_t)r * slab;
+        if constexpr (UPD) {
+          v = (T)((double)z[o] + bt * (double)p[o]);
+          p[o] = v;
+        } else {
+          v = src[o];
+        }
+      }
+      sh[r * C + c] = v;
+    }
+    __syncthreads();
+    for (int l = 1; l <= J; ++l) {
+      const int s = N >> l;
+      const T cl = (T)exp2(0.5 * (double)l);
+      const int items = 1 << (l - 1);
+      const LevelRun run = level_run(items, g, RG);
+      T hl = T(0), hr = T(0);
+      if (run.k0 < run.k1) {
+        if (run.k0 > 0) hl = sh[(2 * run.k0 - 1) * s * C + c];
+        hr = sh[2 * run.k1 * s * C + c];
+      }
+      __syncthreads();
+      if (run.k0 < run.k1) {
+        T e_old = sh[2 * run.k0 * s * C + c];
+        T e_acc = run.k0 > 0 ? e_old - cl * T(boundary_weight(2 * run.k0 * s, N)) * hl : e_old;
+        for (int k = run.k0; k < run.k1; ++k) {
+          const int m = (2 * k + 1) * s;
+          const T d = sh[m * C + c];
+          const T r_old = k + 1 < run.k1 ? sh[(m + s) * C + c] : hr;
+          sh[m * C + c] = T(0.5) * (e_old + r_old) + cl * d;
+          e_acc -= cl * T(boundary_weight(m - s, N)) * d;
+          sh[(m - s) * C + c] = e_acc;
+          e_old = r_old;
+          e_acc = r_old - cl * T(boundary_weight(m + s, N)) * d;
+        }
+        if (run.k1 == items) sh[N * C + c] = e_acc;
+      }
+      __syncthreads();
+    }
+    if (ok) {
+#pragma unroll 4
+      for (int r = g; r <= N; r += RG) dst[off + (int64_t)r * slab] = sh[r * C + c];
+    }
+    __syncthreads();  // the next group's rows overwrite sh
+  }
+}
+
+template <typename T, bool DOT, int JMAX>
+__global__ __launch_bounds__(kLdsThreads) void wavelet_ana_lds_kernel(T* __restrict__ X,
+                                                                      const T* __restrict__ p,
+                                                                      double* __restrict__ partials,
+                                                                      int J, int K) {
+  constexpr int C = lds_cols<T>();
+  constexpr int RG = kLdsThreads / C;
+  __shared__ T sh[((1 << JMAX) + 1) * C];
+  const int64_t slab = slab_elems(K);
+  const int N = 1 << J;
+  const int c = threadIdx.x % C, g = threadIdx.x / C;
+  const int64_t groups = (slab + C - 1) / C;
+  double acc = 0.0;
+  for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+    const int64_t col = grp * C + c;
+    const bool ok = col < slab;
+    const int64_t off = (int64_t)blockIdx.y * (N + 1) * slab + col;
+#pragma unroll 4
+    for (int r = g; r <= N; r += RG) sh[r * C + c] = ok ? X[off + (int64_t)r * slab] : T(0);
+    __syncthreads();
+    for (int l = J; l >= 1; --l) {
+      const int s = N >> l;
+      const T cl = (T)exp2(0.5 * (double)l);
+      const int items = 1 << (l - 1);
+      const LevelRun run = level_run(items, g, RG);
+      T hl = T(0), hr = T(0);
+      if (run.k0 < run.k1) {
+        if (run.k0 > 0) hl = sh[(2 * run.k0 - 1) * s * C + c];
+        hr = sh[2 * run.k1 * s * C + c];
+      }
+      __syncthreads();
+      if (run.k0 < run.k1) {
+        T e_old = sh[2 * run.k0 * s * C + c];
+        T e_acc = run.k0 > 0 ? e_old + T(0.5) * hl : e_old;
+        for (int k = run.k0; k < run.k1; ++k) {
+          const int m = (2 * k + 1) * s;
+          const T yo = sh[m * C + c];
+          const T r_old = k + 1 < run.k1 ? sh[(m + s) * C + c] : hr;
+          sh[m * C + c] = cl * ((yo - T(boundary_weight(m - s, N)) * e_old) -
+                                T(boundary_weight(m + s, N)) * r_old);
+          e_acc += T(0.5) * yo;
+          sh[(m - s) * C + c] = e_acc;
+          e_old = r_old;
+          e_acc = r_old + T(0.5) * yo;
+        }
+        if (run.k1 == items) sh[N * C + c] = e_acc;
+      }
+      __syncthreads();
+    }
+    if (ok) {
+#pragma unroll 4
+      for (int r = g; r <= N; r += RG) {
+        const int64_t o = off + (int64_t)r * slab;
+        const T v = sh[r * C + c];
+        X[o] = v;
+        if constexpr (DOT) acc += (double)p[o] * (double)v;
+      }
+    }
+    __syncthreads();
+  }
+  if constexpr (DOT) {
+    acc = block_sum_n<kLdsThreads>(acc);
     if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
   }
 }
@@ -551,39 +734,90 @@ hipError_t apply_M(hipStream_t s, const T* x, T* y, int K, int rows) {
   return hipGetLastError();
 }
 
+// Workgroups of the LDS-resident transform per right-hand side.
 template <typename T>
-hipError_t wavelet(hipStream_t s, T* X, int J, int K, int nrhs, bool synthesis) {
-  if (J == 0) return hipSuccess;
+int lds_grid(int K) {
+  const int64_t groups = (slab_elems(K) + lds_cols<T>() - 1) / lds_cols<T>();
+  return (int)std::min<int64_t>(groups, kLdsGrid);
+}
+
+// Synthesis launch: in FP64 whole columns in LDS for J <= kLdsJMax (the LDS
+// array is sized for 2^8, 2^9 or 2^10 intervals), one thread per column
+// otherwise.  In FP32 the column kernels measured as fast or faster.
+template <typename T, bool UPD>
+hipError_t launch_syn(hipStream_t s, const T* src, T* dst, T* p, const T* z, const double* beta,
+                      int J, int K, int nrhs) {
+  if constexpr (sizeof(T) == 8) {
+    if (J <= kLdsJMax) {
+      const dim3 grid(lds_grid<T>(K), nrhs);
+      if (J <= 8)
+        wavelet_syn_lds_kernel<T, UPD, 8><<<grid, kLdsThreads, 0, s>>>(src, dst, p, z, beta, J, K);
+      else if (J == 9)
+        wavelet_syn_lds_kernel<T, UPD, 9><<<grid, kLdsThreads, 0, s>>>(src, dst, p, z, beta, J, K);
+      else
+        wavelet_syn_lds_kernel<T, UPD, 10><<<grid, kLdsThreads, 0, s>>>(src, dst, p, z, beta, J,
+                                                                        K);
+      return hipGetLastError();
+    }
+  }
   const dim3 grid(blocks_for(slab_elems(K)), nrhs);
-  if (synthesis)
-    wavelet_syn_kernel<T, false><<<grid, kBlock, 0, s>>>(X, X, nullptr, nullptr, nullptr, J, K);
-  else
-    wavelet_ana_kernel<T, false><<<grid, kBlock, 0, s>>>(X, nullptr, nullptr, J, K);
+  wavelet_syn_kernel<T, UPD><<<grid, kBlock, 0, s>>>(src, dst, p, z, beta, J, K);
+  return hipGetLastError();
+}
+
+// Analysis launch; returns the number of partial sums per right-hand side
+// (with DOT) through nblk.
+template <typename T, bool DOT>
+hipError_t launch_ana(hipStream_t s, T* X, const T* p, double* partials, int J, int K, int nrhs,
+                      int* nblk) {
+  if constexpr (sizeof(T) == 8) {
+    if (J <= kLdsJMax) {
+      const dim3 grid(lds_grid<T>(K), nrhs);
+      *nblk = (int)grid.x;
+      if (J <= 8)
+        wavelet_ana_lds_kernel<T, DOT, 8><<<grid, kLdsThreads, 0, s>>>(X, p, partials, J, K);
+      else if (J == 9)
+        wavelet_ana_lds_kernel<T, DOT, 9><<<grid, kLdsThreads, 0, s>>>(X, p, partials, J, K);
+      else
+        wavelet_ana_lds_kernel<T, DOT, 10><<<grid, kLdsThreads, 0, s>>>(X, p, partials, J, K);
+      return hipGetLastError();
+    }
+  }
+  const dim3 grid(blocks_for(slab_elems(K)), nrhs);
+  *nblk = (int)grid.x;
+  wavelet_ana_kernel<T, DOT><<<grid, kBlock, 0, s>>>(X, p, partials, J, K);
   return hipGetLastError();
 }
 
 template <typename T>
+hipError_t wavelet(hipStream_t s, T* X, int J, int K, int nrhs, bool synthesis) {
+  if (J == 0) return hipSuccess;
+  if (synthesis) return launch_syn<T, false>(s, X, X, nullptr, nullptr, nullptr, J, K, nrhs);
+  int nblk = 0;
+  return launch_ana<T, false>(s, X, nullptr, nullptr, J, K, nrhs, &nblk);
+}
+
+template <typename T>
 hipError_t synthesis(hipStream_t s, const T* src, T* dst, int J, int K, int nrhs) {
-  const dim3 grid(blocks_for(slab_elems(K)), nrhs);
-  wavelet_syn_kernel<T, false><<<grid, kBlock, 0, s>>>(src, dst, nullptr, nullptr, nullptr, J, K);
-  return hipGetLastError();
+  return launch_syn<T, false>(s, src, dst, nullptr, nullptr, nullptr, J, K, nrhs);
 }
 
 template <typename T>
 hipError_t synthesis_update(hipStream_t s, T* p, const T* z, const double* beta, T* X, int J,
                             int K, int nrhs) {
-  const dim3 grid(blocks_for(slab_elems(K)), nrhs);
-  wavelet_syn_kernel<T, true><<<grid, kBlock, 0, s>>>(p, X, p, z, beta, J, K);
-  return hipGetLastError();
+  return launch_syn<T, true>(s, p, X, p, z, beta, J, K, nrhs);
 }
 
-int analysis_dot_blocks(int K) { return (int)blocks_for(slab_elems(K)); }
+int analysis_dot_blocks(int K) {
+  return (int)std::max<int64_t>(blocks_for(slab_elems(K)), kLdsGrid);
+}
 
 template <typename T>
 hipError_t analysis_dot(hipStream_t s, T* X, const T* p, double* partials, double* out, int J,
                         int K, int nrhs) {
-  const int nblk = analysis_dot_blocks(K);
-  wavelet_ana_kernel<T, true><<<dim3(nblk, nrhs), kBlock, 0, s>>>(X, p, partials, J, K);
+  int nblk = 0;
+  const hipError_t e = launch_ana<T, true>(s, X, p, partials, J, K, nrhs, &nblk);
+  if (e != hipSuccess) return e;
   dot_final_kernel<<<nrhs, kBlock, 0, s>>>(partials, nblk, out);
   return hipGetLastError();
 }
