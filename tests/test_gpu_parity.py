@@ -38,8 +38,9 @@ def say(msg):
 
 
 # (J, K): several MG tiles with a ragged tail (K = 6: 63 = 32 + 31 nodes per
-# side; K = 7: 127), single-interval time (J = 0) and the one-node mesh (K = 1)
-OP_CASES = [(0, 1), (1, 2), (2, 3), (3, 6), (2, 7), (5, 4)]
+# side; K = 7: 127), single-interval time (J = 0), the one-node mesh (K = 1) and
+# the longest time axes whose columns fit in LDS (J = 9, 10)
+OP_CASES = [(0, 1), (1, 2), (2, 3), (3, 6), (2, 7), (5, 4), (9, 3), (10, 2)]
 
 
 def _op_input(J, K, seed):
