@@ -207,6 +207,7 @@ __global__ __launch_bounds__(kBlock) void wavelet_ana_kernel(T* __restrict__ X,
 constexpr int kLdsJMax = 10;
 constexpr int kLdsThreads = 1024;
 constexpr int kLdsGrid = 2048;  // workgroups per right-hand side, at most
+constexpr int kBatch = 8;       // rows a thread loads or stores at once
 template <typename T>
 constexpr int lds_cols() {
   return 128 / (int)sizeof(T);
@@ -245,6 +246,7 @@ __global__ __launch_bounds__(kLdsThreads) void wavelet_syn_lds_kernel(const T* s
                                                                       int J, int K) {
   constexpr int C = lds_cols<T>();
   constexpr int RG = kLdsThreads / C;  // threads per column
+  constexpr int B = UPD ? kBatch / 2 : kBatch;  // two loads per row with UPD
   __shared__ T sh[((1 << JMAX) + 1) * C];
   const int64_t slab = slab_elems(K);
   const int N = 1 << J;
@@ -255,20 +257,34 @@ __global__ __launch_bounds__(kLdsThreads) void wavelet_syn_lds_kernel(const T* s
     const int64_t col = grp * C + c;
     const bool ok = col < slab;
     const int64_t off = (int64_t)blockIdx.y * (N + 1) * slab + col;
-    // every row's coefficient (with UPD: p = z + beta p, written back)
-#pragma unroll 4
-    for (int r = g; r <= N; r += RG) {
-      T v = T(0);
-      if (ok) {
-        const int64_t o = off + (int64_t)r * slab;
-        if constexpr (UPD) {
-          v = (T)((double)z[o] + bt * (double)p[o]);
-          p[o] = v;
-        } else {
-          v = src[o];
+    // every row's coefficient (with UPD: p = z + beta p, written back); a
+    // thread issues B rows of loads before it uses the first
+#pragma unroll 1
+    for (int r0 = g; r0 <= N; r0 += B * RG) {
+      T v[B];
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        const int r = r0 + i * RG;
+        v[i] = T(0);
+        if (ok && r <= N) {
+          const int64_t o = off + (int64_t)r * slab;
+          if constexpr (UPD) {
+            v[i] = (T)((double)z[o] + bt * (double)p[o]);
+          } else {
+            v[i] = src[o];
+          }
         }
       }
-      sh[r * C + c] = v;
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        const int r = r0 + i * RG;
+        if (r <= N) {
+          sh[r * C + c] = v[i];
+          if constexpr (UPD) {
+            if (ok) p[off + (int64_t)r * slab] = v[i];
+          }
+        }
+      }
     }
     __syncthreads();
     for (int l = 1; l <= J; ++l) {
@@ -299,9 +315,19 @@ __global__ __launch_bounds__(kLdsThreads) void wavelet_syn_lds_kernel(const T* s
       }
       __syncthreads();
     }
-    if (ok) {
-#pragma unroll 4
-      for (int r = g; r <= N; r += RG) dst[off + (int64_t)r * slab] = sh[r * C + c];
+#pragma unroll 1
+    for (int r0 = g; r0 <= N; r0 += B * RG) {
+      T v[B];
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        const int r = r0 + i * RG;
+        v[i] = r <= N ? sh[r * C + c] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        const int r = r0 + i * RG;
+        if (ok && r <= N) dst[off + (int64_t)r * slab] = v[i];
+      }
     }
     __syncthreads();  // the next group's rows overwrite sh
   }
@@ -314,6 +340,7 @@ __global__ __launch_bounds__(kLdsThreads) void wavelet_ana_lds_kernel(T* __restr
                                                                       int J, int K) {
   constexpr int C = lds_cols<T>();
   constexpr int RG = kLdsThreads / C;
+  constexpr int BS = DOT ? kBatch / 2 : kBatch;  // two loads per row with DOT
   __shared__ T sh[((1 << JMAX) + 1) * C];
   const int64_t slab = slab_elems(K);
   const int N = 1 << J;
@@ -324,8 +351,20 @@ __global__ __launch_bounds__(kLdsThreads) void wavelet_ana_lds_kernel(T* __restr
     const int64_t col = grp * C + c;
     const bool ok = col < slab;
     const int64_t off = (int64_t)blockIdx.y * (N + 1) * slab + col;
-#pragma unroll 4
-    for (int r = g; r <= N; r += RG) sh[r * C + c] = ok ? X[off + (int64_t)r * slab] : T(0);
+#pragma unroll 1
+    for (int r0 = g; r0 <= N; r0 += kBatch * RG) {
+      T v[kBatch];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        const int r = r0 + i * RG;
+        v[i] = ok && r <= N ? X[off + (int64_t)r * slab] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        const int r = r0 + i * RG;
+        if (r <= N) sh[r * C + c] = v[i];
+      }
+    }
     __syncthreads();
     for (int l = J; l >= 1; --l) {
       const int s = N >> l;
@@ -356,13 +395,22 @@ __global__ __launch_bounds__(kLdsThreads) void wavelet_ana_lds_kernel(T* __restr
       }
       __syncthreads();
     }
-    if (ok) {
-#pragma unroll 4
-      for (int r = g; r <= N; r += RG) {
-        const int64_t o = off + (int64_t)r * slab;
-        const T v = sh[r * C + c];
-        X[o] = v;
-        if constexpr (DOT) acc += (double)p[o] * (double)v;
+#pragma unroll 1
+    for (int r0 = g; r0 <= N; r0 += BS * RG) {
+      T v[BS], pv[BS];
+#pragma unroll
+      for (int i = 0; i < BS; ++i) {
+        const int r = r0 + i * RG;
+        v[i] = r <= N ? sh[r * C + c] : T(0);
+        if constexpr (DOT) pv[i] = ok && r <= N ? p[off + (int64_t)r * slab] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < BS; ++i) {
+        const int r = r0 + i * RG;
+        if (ok && r <= N) {
+          X[off + (int64_t)r * slab] = v[i];
+          if constexpr (DOT) acc += (double)pv[i] * (double)v[i];
+        }
       }
     }
     __syncthreads();
