@@ -199,11 +199,11 @@ __global__ __launch_bounds__(kBlock) void wavelet_ana_kernel(T* __restrict__ X,
 // every level runs in LDS, where the column kernels above re-read and
 // re-write rows level by level.  Within a level the odd rows of a column are
 // cut into runs of consecutive odd rows, one run per thread; a run is
-// processed left to right exactly as the column kernels process a whole
-// level (the same operations in the same order, so the results are the
-// same), with the two values it shares with the neighbouring runs -- the
-// odd row just left of it and the even row just right of it -- read before
-// the level starts.
+// processed left to right with the operations the column kernels apply to a
+// whole level, in the same order, and the two values it shares with the
+// neighbouring runs -- the odd row just left of it and the even row just
+// right of it -- are read before the level starts.  The fused dot sums each
+// thread's rows in row order, then the workgroup in a fixed order.
 constexpr int kLdsJMax = 10;
 constexpr int kLdsThreads = 1024;
 constexpr int kLdsGrid = 2048;  // workgroups per right-hand side, at most
