@@ -3,11 +3,13 @@
 
 Metric: PCG unknowns x iterations per second, and time-to-solve at 1e-8
 relative residual (sqrt(r^T K_X r) relative to the first residual), for the
-single FP64 solve with N = 2^10 time intervals and h = 2^-9 (1025 x 261121 =
-267,649,025 unknowns; seeded Fourier forcing, u0 = sin(pi x) sin(pi y)).
-One step = one complete solve (right-hand side, f-hat, PCG, u = W w) with
-the data already resident on the GPU.  The FP32-mixed form of the same solve
-is timed beside it.
+largest single solve: FP64, N = 2^12 time intervals and h = 2^-9 (4097 x
+261121 = 1,069,812,737 unknowns; seeded Fourier forcing, u0 = sin(pi x)
+sin(pi y)).  One step = one complete solve (right-hand side, f-hat, PCG,
+u = W w) with the data already resident on the GPU.  The FP32-mixed form of
+the same solve is timed beside it.  Timed solves run as in production (each
+PCG iteration replayed from a HIP graph); the per-kernel roofline comes from
+one more solve run eagerly with HIP events around every hot launch.
 
 Prints one JSON line.  Only one GPU is used; --gpus > 1 exits with a message.
 """
@@ -40,7 +42,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="heat2d_J10_K9", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="heat2d_J12_K9", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-compare", action="store_true", help="skip the other-precision run")
@@ -79,25 +81,54 @@ def load_inputs(stp, ctx, J, K, nrhs, seed, u0kind, torch):
     torch.cuda.synchronize()
 
 
-def run_solves(stp, ctx, nrhs, tol, steps, warmup, torch, profile=False):
+def _checked(stp, status, st):
+    if status != stp.STP_OK:
+        bad = [(b, s["status"], s["rel_residual"]) for b, s in enumerate(st) if s["status"] != 0]
+        raise SystemExit(f"bench.py: a timed solve did not converge: status {status}, "
+                         f"(rhs, status, rel_residual) {bad[:4]}")
+    return st
+
+
+def run_solves(stp, ctx, nrhs, tol, steps, warmup, torch):
+    """Mean wall time of `steps` solves after `warmup` untimed ones; every
+    solve must converge."""
     for _ in range(warmup):
-        stp.stp_solve(ctx, tol, nrhs)
-    torch.cuda.synchronize()
-    if profile:
-        stp.stp_profile(ctx, True)
+        _checked(stp, *stp.stp_solve(ctx, tol, nrhs))
     stats = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        status, st = stp.stp_solve(ctx, tol, nrhs)
-        stats.append(st)
+        stats.append(_checked(stp, *stp.stp_solve(ctx, tol, nrhs)))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kstats = None
-    if profile:
-        kstats = {k: stp.stp_profile_read(ctx, k) for k in stp.STP_KERNEL_NAMES}
-        stp.stp_profile(ctx, False)
-    return (t1 - t0) / steps, stats, kstats
+    return (t1 - t0) / steps, stats
+
+
+def profile_solve(stp, ctx, nrhs, tol, torch):
+    """Per-kernel launches, device time and algorithmic bytes of one more
+    solve, run eagerly with HIP events around every hot launch."""
+    torch.cuda.synchronize()
+    stp.stp_profile(ctx, True)
+    _checked(stp, *stp.stp_solve(ctx, tol, nrhs))
+    kstats = {k: stp.stp_profile_read(ctx, k) for k in stp.STP_KERNEL_NAMES}
+    stp.stp_profile(ctx, False)
+    return kstats
+
+
+def kernel_table(stp, kst):
+    """Achieved algorithmic GB/s and fraction of the HBM peak per kernel."""
+    out = {}
+    for k, d in kst.items():
+        if d["launches"] == 0:
+            continue
+        avg_ms = d["total_ms"] / d["launches"]
+        per_launch = d["alg_bytes"] / d["launches"]
+        gbs = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+        out[stp.STP_KERNEL_NAMES[k]] = {
+            "launches": d["launches"], "total_ms": round(d["total_ms"], 3),
+            "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": per_launch,
+            "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def measured_traffic(workload, precision, kernel, alg_bytes_per_launch):
@@ -374,8 +405,8 @@ def main():
 
     ctx = stp.stp_create(J, K, nrhs, prec, stream=torch.cuda.current_stream())
     load_inputs(stp, ctx, J, K, nrhs, seed, u0kind, torch)
-    t_step, stats, kst = run_solves(stp, ctx, nrhs, args.tol, args.steps, args.warmup, torch,
-                                    profile=True)
+    t_step, stats = run_solves(stp, ctx, nrhs, args.tol, args.steps, args.warmup, torch)
+    kst = profile_solve(stp, ctx, nrhs, args.tol, torch)
     its = stats[-1][0]["iterations"]
     iters_sum = sum(s["iterations"] for s in stats[-1])
     u_main = None
@@ -385,24 +416,24 @@ def main():
     stp.stp_destroy(ctx)
     print(f"# main: {t_step * 1e3:.1f} ms per solve, iterations {its}", file=sys.stderr, flush=True)
 
-    # roofline of the dominant kernel (largest summed device time)
+    # roofline of the dominant kernel (largest summed device time), and the
+    # achieved rate of every hot kernel
+    table = kernel_table(stp, kst)
     dom = max(kst, key=lambda k: kst[k]["total_ms"])
-    d = kst[dom]
-    avg_ms = d["total_ms"] / max(d["launches"], 1)
-    bytes_per_launch = d["alg_bytes"] / max(d["launches"], 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    d = table[stp.STP_KERNEL_NAMES[dom]]
     roofline = {
         "kernel": stp.STP_KERNEL_NAMES[dom],
         "bound": "hbm",
-        "achieved": round(achieved, 1),
+        "achieved": d["achieved_gbs"],
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "frac": d["frac"],
         "traffic": measured_traffic(args.workload, args.precision, stp.STP_KERNEL_NAMES[dom],
-                                    bytes_per_launch),
-        "avg_launch_ms": round(avg_ms, 4),
-        "alg_bytes_per_launch": bytes_per_launch,
+                                    d["alg_bytes_per_launch"]),
+        "avg_launch_ms": d["avg_launch_ms"],
+        "alg_bytes_per_launch": d["alg_bytes_per_launch"],
         "launches": d["launches"],
+        "kernels": table,
     }
 
     compare = None
@@ -410,7 +441,7 @@ def main():
         other = stp.STP_MIXED if prec == stp.STP_FP64 else stp.STP_FP64
         ctx = stp.stp_create(J, K, nrhs, other, stream=torch.cuda.current_stream())
         load_inputs(stp, ctx, J, K, nrhs, seed, u0kind, torch)
-        t2, st2, _ = run_solves(stp, ctx, nrhs, args.tol, 1, 1, torch)
+        t2, st2 = run_solves(stp, ctx, nrhs, args.tol, 2, 1, torch)
         u2 = torch.zeros_like(u_main)
         stp.stp_get_solution(ctx, 0, u2)
         torch.cuda.synchronize()

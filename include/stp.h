@@ -73,8 +73,13 @@ typedef struct {
 
 typedef struct {
   int iterations;        /* S-hat applications of the (inner) PCG, summed */
-  int outer_iterations;  /* STP_MIXED: FP64 residual evaluations (0 for STP_FP64) */
-  double rel_residual;   /* sqrt(r^T K_X r / f-hat^T K_X f-hat) at exit */
+  int outer_iterations;  /* STP_MIXED: FP64 residuals r = f-hat - S-hat w evaluated,
+                            counting r = f-hat of w = 0 (0 for STP_FP64) */
+  double rel_residual;   /* sqrt(r^T K_X r / f-hat^T K_X f-hat) of the returned w.
+                            STP_FP64: PCG's own r and z.  STP_MIXED: r is the FP64
+                            residual of the returned w, rounded to FP32, and K_X the
+                            FP32 preconditioner, so the value carries the FP32 K_X's
+                            rounding (a relative error of a few 1e-3 at h = 2^-9) */
   double seconds;        /* device time of the solve (HIP events on the stream) */
   int status;            /* per right-hand side: STP_OK, STP_NOT_CONVERGED, STP_E_BREAKDOWN */
 } stp_stats;
@@ -104,8 +109,16 @@ stp_status stp_set_g(stp_ctx* ctx, int rhs, const double* g, int on_device);
  * Returns STP_OK, STP_NOT_CONVERGED (some rhs hit maxit), STP_E_BREAKDOWN. */
 stp_status stp_solve(stp_ctx* ctx, double rel_tol, stp_stats* per_rhs);
 
-/* u = W w of the last solve: (2^J + 1) x N_x nodal values. */
+/* u = W w of the last solve (Section 3.4: the solution of S u = f is
+ * recovered from the wavelet coordinates w of S-hat w = f-hat by one
+ * synthesis): (2^J + 1) x N_x nodal values, written to `u` (host or device
+ * memory of the caller, layout as above).  STP_E_INVALID_ARG before the first
+ * solve, for a NULL `u` or an `rhs` out of range. */
 stp_status stp_get_solution(stp_ctx* ctx, int rhs, double* u, int on_device);
+/* PCG iterations of the last solve of right-hand side `rhs`: the number of
+ * S-hat applications (Section 3.4; in STP_MIXED the inner FP32 iterations,
+ * summed over the refinement steps).  0 before the first solve;
+ * STP_E_INVALID_ARG for a NULL output or an `rhs` out of range. */
 stp_status stp_get_iterations(const stp_ctx* ctx, int rhs, int* iterations);
 
 /* Device bytes held by a context with these sizes (planning / admission). */
@@ -137,11 +150,19 @@ stp_status stp_apply(stp_ctx* ctx, int op, int precision, int rhs,
  * While enabled, the library brackets every launch of its hot kernels with
  * HIP events on the context stream and accumulates, per kernel, the number
  * of launches, their summed device time and their algorithmic HBM bytes
- * (each input element read once, each output element written once).
- * Kernels: STP_KERNEL_MG_PRE and STP_KERNEL_MG_POST on the finest grid. */
-#define STP_KERNEL_MG_PRE   0
-#define STP_KERNEL_MG_POST  1
-#define STP_KERNEL_COUNT    2
+ * (each input element read once, each output element written once, over the
+ * interior nodes).  Profiling runs every PCG iteration eagerly (no graph
+ * replay), so time solves with it off and profile a separate solve.
+ * Kernels (the steps of Section 3.4's iteration and Lemma 4.2's S):        */
+#define STP_KERNEL_MG_PRE        0  /* finest-grid pre-smoothing + restriction (K_x, K_l) */
+#define STP_KERNEL_MG_POST       1  /* finest-grid prolongation + post-smoothing           */
+#define STP_KERNEL_SYN_UPDATE    2  /* X = W (z + beta p), p updated (eq. (11), Section 3.3) */
+#define STP_KERNEL_ANA_DOT       3  /* q = W^T q with p^T q, both passes                    */
+#define STP_KERNEL_TIME_STENCIL  4  /* y1, y2 of Lemma 4.2 (time and space stencils)        */
+#define STP_KERNEL_COMBINE       5  /* M z1 + A z2 (+ Gamma_0 term)                          */
+#define STP_KERNEL_UPDATE_WR     6  /* w += gamma p, r -= gamma q                            */
+#define STP_KERNEL_DOT           7  /* r^T z, both passes                                    */
+#define STP_KERNEL_COUNT         8
 typedef struct {
   int launches;
   double total_ms;
@@ -181,7 +202,10 @@ typedef struct {
 } stp_request;
 /* The buffers of a request are read when the request is admitted and u is
  * written when it finishes; the caller keeps them alive until
- * stp_server_poll reports the request finished. */
+ * stp_server_poll reports the request finished.  The server reads device
+ * buffers on its own streams, which are not ordered after any of the
+ * caller's streams: the values in u0 and g must be complete (the stream or
+ * event that produced them synchronised) before stp_server_submit. */
 
 typedef struct {
   int waiting;                /* requests not yet admitted */

@@ -70,9 +70,12 @@ class stp_kernel_stat(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-STP_KERNEL_MG_PRE = 0
-STP_KERNEL_MG_POST = 1
-STP_KERNEL_NAMES = {STP_KERNEL_MG_PRE: "mg_pre", STP_KERNEL_MG_POST: "mg_post"}
+(STP_KERNEL_MG_PRE, STP_KERNEL_MG_POST, STP_KERNEL_SYN_UPDATE, STP_KERNEL_ANA_DOT,
+ STP_KERNEL_TIME_STENCIL, STP_KERNEL_COMBINE, STP_KERNEL_UPDATE_WR, STP_KERNEL_DOT) = range(8)
+STP_KERNEL_NAMES = {STP_KERNEL_MG_PRE: "mg_pre", STP_KERNEL_MG_POST: "mg_post",
+                    STP_KERNEL_SYN_UPDATE: "syn_update", STP_KERNEL_ANA_DOT: "ana_dot",
+                    STP_KERNEL_TIME_STENCIL: "time_stencil", STP_KERNEL_COMBINE: "combine",
+                    STP_KERNEL_UPDATE_WR: "update_wr", STP_KERNEL_DOT: "dot"}
 
 
 class StpError(RuntimeError):

@@ -288,6 +288,14 @@ stp_status mg_apply(stp_ctx* c, MgScratch<T>& mg, const T* b, T* x, int64_t rows
   return STP_OK;
 }
 
+// Algorithmic bytes of a pass that moves `words` values of type T per
+// interior node of `rows` time rows.
+template <typename T>
+double row_bytes(const stp_ctx* c, int64_t rows, double words) {
+  const double n = (double)grid_n(c->K);
+  return words * sizeof(T) * (double)rows * n * n;
+}
+
 // out = S X (Lemma 4.2) for `nrhs` right-hand sides starting at X.
 template <typename T>
 stp_status S_apply(stp_ctx* c, Ops<T>& o, const T* X, T* out, int nrhs) {
@@ -297,10 +305,16 @@ stp_status S_apply(stp_ctx* c, Ops<T>& o, const T* X, T* out, int nrhs) {
   T* y2 = o.y + v;
   T* z1 = o.z;
   T* z2 = o.z + v;
-  HIP_TRY(time_stencil_pair<T>(c->stream, X, y1, y2, c->J, c->K, nrhs));
+  // X in; y1, y2 out
+  STP_TRY(timed_launch(c, STP_KERNEL_TIME_STENCIL, row_bytes<T>(c, rows, 3.0), [&] {
+    return time_stencil_pair<T>(c->stream, X, y1, y2, c->J, c->K, nrhs);
+  }));
   // y1 | y2 and z1 | z2 are contiguous: one K_x application over both
   STP_TRY(mg_apply<T>(c, o.mg, y1, z1, 2 * rows, 1.0, nullptr));
-  HIP_TRY(combine<T>(c->stream, z1, z2, X, c->per_rhs, out, c->J, c->K, nrhs));
+  // z1, z2 in; S X out (row 0's M X_0 term is one row in 2^J + 1)
+  STP_TRY(timed_launch(c, STP_KERNEL_COMBINE, row_bytes<T>(c, rows, 3.0), [&] {
+    return combine<T>(c->stream, z1, z2, X, c->per_rhs, out, c->J, c->K, nrhs);
+  }));
   return STP_OK;
 }
 
@@ -318,9 +332,15 @@ stp_status Shat_apply(stp_ctx* c, Ops<T>& o, const T* p, T* out, int nrhs) {
 // pq = p^T q (fused into the analysis).
 template <typename T>
 stp_status Shat_iteration(stp_ctx* c, Ops<T>& o, PcgVecs<T>& v) {
-  HIP_TRY(synthesis_update<T>(c->stream, v.p, v.z, c->sc.beta, o.X, c->J, c->K, c->nrhs));
+  // z, p in; p, X out
+  STP_TRY(timed_launch(c, STP_KERNEL_SYN_UPDATE, row_bytes<T>(c, c->rows, 4.0), [&] {
+    return synthesis_update<T>(c->stream, v.p, v.z, c->sc.beta, o.X, c->J, c->K, c->nrhs);
+  }));
   STP_TRY(S_apply<T>(c, o, o.X, v.q, c->nrhs));
-  HIP_TRY(analysis_dot<T>(c->stream, v.q, v.p, c->partials, c->sc.pq, c->J, c->K, c->nrhs));
+  // q, p in; q out
+  STP_TRY(timed_launch(c, STP_KERNEL_ANA_DOT, row_bytes<T>(c, c->rows, 3.0), [&] {
+    return analysis_dot<T>(c->stream, v.q, v.p, c->partials, c->sc.pq, c->J, c->K, c->nrhs);
+  }));
   return STP_OK;
 }
 
@@ -389,9 +409,15 @@ stp_status pcg_iteration(stp_ctx* c, PcgVecs<T>& v) {
   const int64_t n = c->per_rhs;
   STP_TRY(Shat_iteration<T>(c, o, v));
   HIP_TRY(pcg_gamma(c->stream, c->sc, nrhs));
-  HIP_TRY(update_wr<T>(c->stream, v.w, v.r, v.p, v.q, c->sc.gamma, n, nrhs));
+  // w, r, p, q in; w, r out
+  STP_TRY(timed_launch(c, STP_KERNEL_UPDATE_WR, row_bytes<T>(c, c->rows, 6.0), [&] {
+    return update_wr<T>(c->stream, v.w, v.r, v.p, v.q, c->sc.gamma, n, nrhs);
+  }));
   STP_TRY(KX_apply<T>(c, o, v.r, v.z, nrhs));
-  HIP_TRY(dot<T>(c->stream, v.r, v.z, n, nrhs, c->partials, c->sc.rhonew));
+  // r, z in
+  STP_TRY(timed_launch(c, STP_KERNEL_DOT, row_bytes<T>(c, c->rows, 2.0), [&] {
+    return dot<T>(c->stream, v.r, v.z, n, nrhs, c->partials, c->sc.rhonew);
+  }));
   HIP_TRY(pcg_beta(c->stream, c->sc, nrhs, c->opt.maxit));
   return STP_OK;
 }
@@ -512,7 +538,11 @@ void collect_stats(stp_ctx* c) {
 }
 
 // Mixed form: outer step k > 0 starts from the FP64 residual f-hat - S-hat w.
-stp_status mixed_outer_start(stp_ctx* c, int k) {
+// The stopping quantity r^T K_X r is taken with the FP32 K_X on the residual
+// rounded to FP32 (the inner PCG start computes it anyway); relative to the
+// same quantity of the first step its rounding largely cancels.  `last`: the
+// refinement-step limit is reached, so this evaluation only reports.
+stp_status mixed_outer_start(stp_ctx* c, int k, bool last) {
   PcgVecs<float>& v = c->pcg32;
   if (k > 0) {
     STP_TRY(Shat_apply<double>(c, c->ops64, c->w64, c->r64, c->nrhs));
@@ -520,7 +550,7 @@ stp_status mixed_outer_start(stp_ctx* c, int k) {
   }
   HIP_TRY((cast<double, float>(c->stream, c->r64, v.rhs, c->vec)));
   STP_TRY(pcg_init<float>(c, v, v.rhs, nullptr));
-  HIP_TRY(mixed_adjust(c->stream, c->sc, c->ms, c->nrhs, c->tolv, c->opt.inner_tol, k));
+  HIP_TRY(mixed_adjust(c->stream, c->sc, c->ms, c->nrhs, c->tolv, c->opt.inner_tol, k, last));
   return STP_OK;
 }
 
@@ -544,13 +574,24 @@ stp_status drive_begin(stp_ctx* c, const double* tol) {
     HIP_TRY(mixed_reset(c->stream, c->ms, nr));
     HIP_TRY(hipMemsetAsync(c->w64, 0, sizeof(double) * c->vec, c->stream));
     HIP_TRY(copy<double>(c->stream, c->fhat, c->r64, c->vec));
-    STP_TRY(mixed_outer_start(c, 0));
+    STP_TRY(mixed_outer_start(c, 0, false));
   }
   c->drv.phase = stp_ctx::kIter;
   c->drv.outer_k = 0;
   c->drv.adjusted = true;
   STP_TRY(post_flags(c));
   return STP_OK;
+}
+
+// K_x (vcycles V-cycles from zero for A_x) on `rows` slabs of level K, with
+// the multigrid work space the caller provides (no allocation).
+stp_status kspace_apply_slabs(hipStream_t s, MgScratch<double>& mg, const double* b, double* x,
+                              int K, int rows, int vcycles) {
+  stp_ctx c;
+  c.K = K;
+  c.stream = s;
+  c.opt.vcycles = vcycles;
+  return mg_apply<double>(&c, mg, b, x, rows, 1.0, nullptr);
 }
 
 // Whether the last unit has completed (never blocks).
@@ -583,13 +624,16 @@ stp_status drive_next(stp_ctx* c) {
     return post_flags(c);
   }
   if (c->prec == STP_FP64 || d.adjusted) return finish_unit(c);
-  // mixed: the inner solve has ended; refine w and start the next outer step
+  // mixed: the inner solve has ended; refine w and start the next outer step.
+  // At the step limit the residual of the refined w is still evaluated, so
+  // that the reported residual belongs to the returned solution.
   HIP_TRY(mixed_inner_done(c->stream, c->sc, c->ms, c->nrhs));
   HIP_TRY(add_correction(c->stream, c->w64, c->pcg32.w, c->per_rhs, c->nrhs, c->ms.status));
-  if (d.outer_k + 1 >= c->opt.max_outer) return finish_unit(c);
   d.outer_k += 1;
-  STP_TRY(mixed_outer_start(c, d.outer_k));
+  const bool last = d.outer_k >= c->opt.max_outer;
+  STP_TRY(mixed_outer_start(c, d.outer_k, last));
   d.adjusted = true;
+  if (last) return finish_unit(c);
   return post_flags(c);
 }
 

@@ -134,9 +134,10 @@ struct MixedState {
 };
 hipError_t mixed_reset(hipStream_t s, MixedState ms, int nrhs);
 // after the inner PCG start of outer step k: convergence test of the FP64
-// residual against tol_b, inner target max(inner_tol sqrt(rho0), tol_b/2 sqrt(rho0_first))
+// residual against tol_b, inner target max(inner_tol sqrt(rho0), tol_b/2 sqrt(rho0_first));
+// last: no further inner solve (the right-hand sides not converged stop unconverged)
 hipError_t mixed_adjust(hipStream_t s, PcgScalars sc, MixedState ms, int nrhs, const double* tol,
-                        double inner_tol, int k);
+                        double inner_tol, int k, bool last);
 // after an inner solve: inner_its += its, breakdown marks the right-hand side done
 hipError_t mixed_inner_done(hipStream_t s, PcgScalars sc, MixedState ms, int nrhs);
 

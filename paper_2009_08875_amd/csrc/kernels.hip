@@ -650,7 +650,8 @@ __global__ void pcg_beta_kernel(PcgScalars sc, int nrhs, int maxit) {
 // right-hand side whether the FP64 residual already meets the tolerance, and
 // set the inner stopping target.
 __global__ void mixed_adjust_kernel(PcgScalars sc, MixedState ms, int nrhs,
-                                    const double* __restrict__ tol, double inner_tol, int k) {
+                                    const double* __restrict__ tol, double inner_tol, int k,
+                                    int last) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nrhs) return;
   if (ms.done[b]) {
@@ -674,7 +675,8 @@ __global__ void mixed_adjust_kernel(PcgScalars sc, MixedState ms, int nrhs,
     ms.status[b] = 0;
     sc.active[b] = 0;
   } else {
-    sc.active[b] = 1;
+    // at the refinement-step limit the solve ends unconverged (done stays 0)
+    sc.active[b] = last ? 0 : 1;
   }
   // stop the inner solve at a relative reduction of inner_tol, but not below
   // what the outer tolerance still needs
@@ -978,8 +980,9 @@ hipError_t mixed_reset(hipStream_t s, MixedState ms, int nrhs) {
   return hipGetLastError();
 }
 hipError_t mixed_adjust(hipStream_t s, PcgScalars sc, MixedState ms, int nrhs, const double* tol,
-                        double inner_tol, int k) {
-  mixed_adjust_kernel<<<blocks_for(nrhs, 64), 64, 0, s>>>(sc, ms, nrhs, tol, inner_tol, k);
+                        double inner_tol, int k, bool last) {
+  mixed_adjust_kernel<<<blocks_for(nrhs, 64), 64, 0, s>>>(sc, ms, nrhs, tol, inner_tol, k,
+                                                          last ? 1 : 0);
   return hipGetLastError();
 }
 hipError_t mixed_inner_done(hipStream_t s, PcgScalars sc, MixedState ms, int nrhs) {

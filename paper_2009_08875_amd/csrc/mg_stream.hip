@@ -706,8 +706,10 @@ hipError_t launch(hipStream_t s, const T* xin, const T* b, const T* ec, T* xout,
                   int rows, double a, const double* sigma) {
   constexpr int H = PRE ? kHaloPre : (WRITE_A ? kHaloPostA : kHaloPost);
   auto kernel = mg_stream_kernel<T, PRE, XIN, DIAG, WRITE_A>;
-  static int slots = -1;  // per kernel instantiation; the library drives one device type
-  if (slots < 0) slots = resident_waves(kernel);
+  // per kernel instantiation (the library drives one device type); a
+  // function-local static is initialised exactly once even when the server's
+  // worker and caller threads launch concurrently
+  static const int slots = resident_waves(kernel);
   const int n = grid_n(l);
   const int ns = strip_count(n, H);
   // Candidate group counts (all give the same result): G groups that split

@@ -142,4 +142,11 @@ stp_status drive_begin(stp_ctx* c, const double* tol);
 bool drive_ready(stp_ctx* c);
 stp_status drive_wait(stp_ctx* c);
 stp_status drive_next(stp_ctx* c);
+
+// K_x (`vcycles` V-cycles from zero for A_x, Section 3.1) on `rows` slabs of
+// level K held in b, result in x, using the multigrid work space in mg
+// (mg.K == K; mg.chunk_rows >= 1; rows are processed mg.chunk_rows at a time).
+// Allocates nothing.
+stp_status kspace_apply_slabs(hipStream_t s, MgScratch<double>& mg, const double* b, double* x,
+                              int K, int rows, int vcycles);
 }  // namespace stp

@@ -14,6 +14,7 @@ namespace {
 
 std::mutex g_mu;
 std::map<uint64_t, int> g_choice;
+thread_local bool t_no_tuning = false;
 
 bool env_flag(const char* name, bool dflt) {
   const char* v = std::getenv(name);
@@ -30,6 +31,7 @@ int tuned(uint64_t key, int candidates, int fallback, hipStream_t stream,
     auto it = g_choice.find(key);
     if (it != g_choice.end()) return it->second;
   }
+  if (t_no_tuning) return fallback;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
     return fallback;
@@ -67,6 +69,9 @@ int tuned(uint64_t key, int candidates, int fallback, hipStream_t stream,
   g_choice[key] = best;
   return best;
 }
+
+NoTuning::NoTuning() : prev_(t_no_tuning) { t_no_tuning = true; }
+NoTuning::~NoTuning() { t_no_tuning = prev_; }
 
 int tuned_choice(uint64_t key, int fallback) {
   std::lock_guard<std::mutex> lk(g_mu);

@@ -26,6 +26,19 @@ int tuned(uint64_t key, int candidates, int fallback, hipStream_t stream,
 // launches that update their output in place and so cannot be repeated).
 int tuned_choice(uint64_t key, int fallback);
 
+// While an object of this type lives on a thread, tuned() on that thread
+// behaves like tuned_choice(): no trial launches, events or waits (for entry
+// points that must only enqueue work).
+struct NoTuning {
+  NoTuning();
+  ~NoTuning();
+  NoTuning(const NoTuning&) = delete;
+  NoTuning& operator=(const NoTuning&) = delete;
+
+ private:
+  bool prev_;
+};
+
 inline uint64_t tune_key(uint64_t a, uint64_t b, uint64_t c, uint64_t d) {
   return (a << 56) ^ (b << 40) ^ (c << 24) ^ d;
 }

@@ -64,11 +64,16 @@ def _wait(stp, server, ids, timeout=120.0):
 
 
 # (J, K, precision, tol, seed): three of one shape (batched together), other
-# shapes, both precisions, tolerances 1e-6 .. 1e-10
+# shapes, both precisions, tolerances 1e-6 .. 1e-10; the K = 6 and K = 7
+# requests (two of them grouped) run the streaming multigrid kernels, whose
+# launch shapes the tuner picks per number of rows, so a group of two gets
+# other shapes than a solo solve
 MIX = [
     (3, 5, "FP64", 1e-8, 201), (3, 5, "FP64", 1e-6, 202), (3, 5, "FP64", 1e-10, 203),
     (4, 4, "MIXED", 1e-8, 204), (2, 6, "FP64", 1e-9, 205), (5, 3, "MIXED", 1e-7, 206),
     (3, 5, "MIXED", 1e-8, 207), (0, 1, "FP64", 1e-8, 208),
+    (4, 7, "FP64", 1e-8, 209), (4, 7, "FP64", 1e-9, 210), (4, 7, "MIXED", 1e-8, 211),
+    (5, 6, "MIXED", 1e-8, 212),
 ]
 
 
