@@ -171,6 +171,29 @@ typedef struct {
 stp_status stp_profile(stp_ctx* ctx, int enable);          /* enabling also clears */
 stp_status stp_profile_read(stp_ctx* ctx, int kernel, stp_kernel_stat* out);
 
+/* ---- K_x without device allocation -------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Computes
+ * what stp_apply(STP_OP_KSPACE) computes in FP64 -- K_x, two V-cycles from
+ * zero for A_x (Section 3.1, Section 5.1), on every one of `rows` rows of
+ * N_x = (2^K - 1)^2 nodal values -- without a context.
+ *   in, out:   device pointers on the current device, rows x N_x FP64 values
+ *              each (layout as above), owned by the caller; must not overlap.
+ *   hip_stream: the hipStream_t the work is enqueued on (NULL = null stream);
+ *              the call returns without waiting for it.
+ * Every intermediate lives in one fixed device array of
+ * STP_STATIC_SCRATCH_BYTES bytes that the library holds on each device it
+ * runs on until the process ends; rows are processed in chunks that fit it
+ * (a row of level K takes about 32 (2^K)^2 bytes), so any `rows` works.
+ * The call makes no hipMalloc, hipFree or other allocation, no trial launches
+ * of the launch-shape tuner, and no wait.  All calls on one device share the
+ * array: calls that overlap in time on one device race and must be ordered
+ * (one stream, or events).  Errors: STP_E_INVALID_ARG (K outside [1, 10],
+ * rows < 0, a NULL buffer), STP_E_DEVICE (no current device, launch failure). */
+#define STP_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+stp_status stp_kspace_apply_static(int K, int rows, const double* in, double* out,
+                                   void* hip_stream);
+
 /* ---- serving: continuous batching of independent solves ------------------
  * Not in the paper (its method solves one problem at a time); this is the
  * request loop around the same solver.  A server owns a device byte budget,

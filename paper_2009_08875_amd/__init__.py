@@ -117,6 +117,7 @@ def _load():
         "stp_server_drain": [vp],
         "stp_server_info": [vp, ctypes.POINTER(stp_server_stats)],
         "stp_server_destroy": [vp],
+        "stp_kspace_apply_static": [i, i, vp, vp, vp],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -253,6 +254,20 @@ def stp_status_string(status):
 
 def stp_last_error():
     return _lib.stp_last_error().decode()
+
+
+STP_STATIC_SCRATCH_BYTES = 256 << 20
+
+
+def stp_kspace_apply_static(K, rows, inp, out, stream=None):
+    """K_x on `rows` rows (device tensors of rows x N_x float64), every
+    intermediate in the library's fixed device array: no allocation."""
+    n = grid_n(K) ** 2
+    pi, dev_i = _ptr(inp, rows * n)
+    po, dev_o = _ptr(out, rows * n)
+    if not (dev_i and dev_o):
+        raise TypeError("stp_kspace_apply_static takes device tensors")
+    return _check(_lib.stp_kspace_apply_static(K, rows, pi, po, _stream(stream)))
 
 
 # ------------------------------------------------------------ serving C-ABI
