@@ -288,15 +288,91 @@ def _kappa_direct(J, K, alpha=0.3):
     return ev.max() / ev.min()
 
 
+def _kappa_matrix_free(J, K, alpha=0.3):
+    """kappa_2(K_X S-hat) with direct inverses for sizes where dense matrices
+    of the whole space-time system are too large: the extreme eigenvalues of
+    the symmetric form L^T S-hat L, K_X = L L^T (blockwise Cholesky), by
+    ARPACK.  S (Lemma 4.2 with K_x = A_x^{-1}) acts through the Kronecker
+    identity (T (x) B) vec(X) = vec(T X B) for symmetric B, on dense P1
+    matrices from element-by-element assembly."""
+    from scipy.sparse.linalg import LinearOperator, eigsh
+
+    N = 2 ** J
+    At, Mt, L, G = temporal.dense(N)
+    A, M = bf.p1_assembly(K)
+    Ai = np.linalg.inv(A)
+    MAM = M @ Ai @ M
+    Wt = bf.wavelet_basis_matrix(J)
+    lev = wavelet.row_levels(J)
+    chol = {}
+    for l in set(int(v) for v in lev):
+        Ci = np.linalg.inv(alpha * A + 2.0 ** l * M)
+        chol[l] = np.linalg.cholesky(Ci @ A @ Ci)
+    Lrow = [chol[int(l)] for l in lev]
+    nx = A.shape[0]
+
+    def S(X):
+        return At @ X @ MAM + Mt @ X @ A + L.T @ X @ M + L @ X @ M + G @ X @ M
+
+    def B(v):
+        V = v.reshape(N + 1, nx)
+        Y = np.stack([Lrow[i] @ V[i] for i in range(N + 1)])
+        Z = Wt.T @ S(Wt @ Y)
+        return np.stack([Lrow[i].T @ Z[i] for i in range(N + 1)]).ravel()
+
+    op = LinearOperator(((N + 1) * nx,) * 2, matvec=B, dtype=np.float64)
+    hi = eigsh(op, k=1, which="LA", tol=1e-12, return_eigenvectors=False)[0]
+    lo = eigsh(op, k=1, which="SA", tol=1e-12, return_eigenvectors=False)[0]
+    return hi / lo
+
+
+def test_matrix_free_kappa_equals_dense_eigensolve():
+    """The matrix-free estimate reproduces the dense generalised eigensolve."""
+    k = _kappa_direct(4, 3)
+    assert abs(_kappa_matrix_free(4, 3) - k) <= 1e-8 * k
+
+
 @pytest.mark.slow
 def test_table1_condition_number():
     """kappa_2(K_X S-hat) with direct inverses, alpha = 0.3, N_t = 65 dofs,
-    N_x = 49 (Table 1 prints 6.34)."""
+    N_x = 49 by a dense generalised eigensolve (Table 1 prints 6.34)."""
     with open(os.path.join(GOLDEN, "table1_kappa.json")) as f:
         gold = json.load(f)
     cell = gold["cells"]["Nt65_Nx49"]
     k = _kappa_direct(6, 3)
     assert abs(k - cell["kappa"]) <= gold["tolerance_abs"]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("cell", ["Nt65_Nx49", "Nt129_Nx49", "Nt257_Nx49", "Nt65_Nx225"])
+def test_table1_all_cells(cell):
+    """Every stored cell of Table 1 (growth with N_t at N_x = 49, and the
+    N_x = 225 column), by the matrix-free eigenvalue computation."""
+    with open(os.path.join(GOLDEN, "table1_kappa.json")) as f:
+        gold = json.load(f)
+    c = gold["cells"][cell]
+    k = _kappa_matrix_free(c["J"], c["K"])
+    assert abs(k - c["kappa"]) <= gold["tolerance_abs"], (cell, k)
+
+
+def test_KX_equals_dense_multigrid_blocks():
+    """K_X of Theorem 3.1 with the multigrid K_l: row i of K_X R equals
+    K_l A K_l r_i with K_l the dense matrix of the sequential-Gauss-Seidel
+    multigrid (tests/bruteforce.py) for alpha A + 2^l M, l = level of row i."""
+    J, K = 3, 3
+    P = Problem(J, K)
+    R = np.random.default_rng(8).standard_normal(P.shape)
+    got = P.KX(R)
+    A, _ = bf.p1_assembly(K)
+    lev = wavelet.row_levels(J)
+    mats = {}
+    for i in range(P.N + 1):
+        l = int(lev[i])
+        if l not in mats:
+            mats[l] = bf.dense_mg_matrix(K, 0.3, 2.0 ** l)
+        Kl = mats[l]
+        ref = Kl @ A @ Kl @ R[i].ravel()
+        assert np.allclose(got[i].ravel(), ref, rtol=0, atol=1e-13 * np.abs(ref).max()), i
 
 
 # ---------------------------------------- exact solution and convergence order
