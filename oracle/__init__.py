@@ -23,7 +23,10 @@ square with lowest-order elements in space and time:
                       S-hat = W^T S W and f-hat = W^T f (Section 3.4), K_X
                       (Theorem 3.1);
   * ``pcg``        -- PCG on S-hat w = f-hat with K_X and the stopping test
-                      of Section 3.4.
+                      of Section 3.4, from zero or from an initial guess;
+  * ``nested``     -- nested iteration over meshes (J - d, K - d) with a
+                      tolerance that tracks the discretisation error
+                      (Section 4.2).
 
 Readings where the paper is silent (listed with reasons in the design notes):
 the three-colour Gauss-Seidel ordering, pre-smoothing forward and
@@ -34,8 +37,10 @@ weights; nodal interpolation of g and u0; the relative stopping test.
 Parity status: every function here is pinned by the CPU tests (brute-force
 finite-element assembly, basis evaluation, Lemma 4.1 with an explicit
 Legendre basis, closed forms, the one-node worked example, dense solves, the
-exact decaying solution, Table 1).  The solution values at the benchmark
+exact decaying solution, Table 1; the nested iteration's mesh transfer by
+direct evaluation of the basis functions, its fixed point by PCG from zero,
+and its error against the exact solution).  The solution values at the benchmark
 sizes are not printed in the paper: the pins above are what fixes them.
 """
-from . import temporal, spatial, multigrid, wavelet, schur, pcg  # noqa: F401
+from . import temporal, spatial, multigrid, wavelet, schur, pcg, nested  # noqa: F401
 from .pcg import solve  # noqa: F401

@@ -18,18 +18,25 @@ def dot(a, b):
     return float(np.sum(a * b))
 
 
-def pcg(P: Problem, fhat, tol=1e-8, maxit=100, callback=None):
-    """Standard Hestenes-Stiefel PCG from ``w = 0``.  Returns ``(w, iterations,
-    history)`` where ``iterations`` counts applications of S-hat and
-    ``history`` holds ``sqrt(r_k^T K_X r_k)`` for k = 0..iterations."""
-    w = np.zeros_like(fhat)
-    r = fhat.copy()
+def pcg(P: Problem, fhat, tol=1e-8, maxit=100, callback=None, w0=None):
+    """Standard Hestenes-Stiefel PCG from ``w = 0``, or from the initial guess
+    ``w0``.  Returns ``(w, iterations, history)`` where ``iterations`` counts
+    applications of S-hat and ``history`` holds ``sqrt(r_k^T K_X r_k)`` for
+    k = 0..iterations.  The stopping test is relative to the data,
+    ``sqrt(r_k^T K_X r_k) <= tol sqrt(f-hat^T K_X f-hat)``, which for
+    ``w0 = 0`` is the first residual's quantity."""
+    if w0 is None:
+        w = np.zeros_like(fhat)
+        r = fhat.copy()
+    else:
+        w = np.array(w0, dtype=np.float64, copy=True)
+        r = fhat - P.Shat(w)
     z = P.KX(r)
     rho = dot(r, z)
     hist = [np.sqrt(max(rho, 0.0))]
     if rho == 0.0:
         return w, 0, hist
-    rho0 = rho
+    rho0 = rho if w0 is None else dot(fhat, P.KX(fhat))
     p = z.copy()
     k = 0
     while k < maxit and not (tol > 0 and np.sqrt(rho) <= tol * np.sqrt(rho0)):

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
+import synth
 from oracle import multigrid, spatial, temporal, wavelet
 from oracle.schur import Problem
 from tests import bruteforce as bf
@@ -377,16 +378,20 @@ def test_KX_equals_dense_multigrid_blocks():
 
 # ---------------------------------------- exact solution and convergence order
 
-def _xnorm_error(J, K):
+def _xnorm_error(J, K, solver=None):
     """Computable X-norm surrogate of u - u_h for u = exp(-2 pi^2 t) sin(pi x) sin(pi y):
     ||grad e||^2 + ||d_t e||^2 / lambda_1 + ||e(1)||^2 (L2 over space-time;
-    lambda_1 = 2 pi^2 bounds the dual-norm part by Poincare)."""
+    lambda_1 = 2 pi^2 bounds the dual-norm part by Poincare).  u_h is the
+    oracle's solution to 1e-12, or solver(J, K, u0) when given."""
     lam = 2.0 * np.pi ** 2
     n = 2 ** K - 1
     h = 2.0 ** -K
     x = np.arange(1, n + 1) * h
     u0 = np.outer(np.sin(np.pi * x), np.sin(np.pi * x))
-    uh, its, _ = oracle.solve(J, K, None, u0, tol=1e-12, maxit=200)
+    if solver is None:
+        uh, its, _ = oracle.solve(J, K, None, u0, tol=1e-12, maxit=200)
+    else:
+        uh = solver(J, K, u0)
     N = 2 ** J
     tau = 1.0 / N
     At, Mt, _ = bf.temporal_by_quadrature(N)
@@ -452,3 +457,73 @@ def test_iterations_bounded_under_refinement():
     assert all(d <= 4 for d in steps)            # at most 2 more iterations per doubling of N
     assert steps[-1] <= steps[0]                 # and the growth slows down
     assert max(its_x) - min(its_x) <= 4                         # near-flat in space
+
+
+# ------------------------------------------------ nested iteration (Section 4.2)
+
+def test_pcg_from_an_initial_guess():
+    """PCG started from the discrete solution stops at once; started from any
+    other guess it reaches the same solution as from zero (Section 3.4)."""
+    from oracle.pcg import pcg
+
+    J, K = 3, 3
+    P = Problem(J, K)
+    fhat = P.WT(P.rhs(synth.fourier_g(J, K, 4), synth.smooth_u0(K, 4)))
+    w_ref, _, _ = pcg(P, fhat, 1e-13, 200)
+    _, k, _ = pcg(P, fhat, 1e-6, 200, w0=w_ref)
+    assert k == 0
+    w, k, _ = pcg(P, fhat, 1e-12, 200, w0=np.random.default_rng(1).standard_normal(P.shape))
+    assert k > 0 and np.linalg.norm(w - w_ref) <= 1e-9 * np.linalg.norm(w_ref)
+
+
+@pytest.mark.parametrize("J,K", [(2, 2), (3, 3), (4, 2)])
+def test_nested_prolongation_embeds_the_coarse_function(J, K):
+    """The coarse solution carried to the finer mesh represents the same
+    function: evaluated through the fine wavelet basis it equals the coarse
+    function's nodal values interpolated linearly in time and by P1 in space
+    (basis functions and hats evaluated directly, tests/bruteforce.py)."""
+    from oracle import nested
+
+    m = 2 ** (K - 1) - 1
+    w = np.random.default_rng(J + K).standard_normal((2 ** (J - 1) + 1, m, m))
+    fine = nested.prolong(w)
+    Wf = bf.wavelet_basis_matrix(J)
+    Wc = bf.wavelet_basis_matrix(J - 1)
+    Ps = bf.prolongation_by_evaluation(K)
+    uc = np.einsum("ti,ijk->tjk", Wc, w).reshape(2 ** (J - 1) + 1, -1)   # coarse nodal values
+    tc = np.arange(2 ** (J - 1) + 1) / 2 ** (J - 1)
+    tf = np.arange(2 ** J + 1) / 2 ** J
+    ut = np.stack([np.interp(tf, tc, uc[:, k]) for k in range(uc.shape[1])], 1)
+    ref = ut @ Ps.T
+    got = np.einsum("ti,ijk->tjk", Wf, fine).reshape(2 ** J + 1, -1)
+    assert np.allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_nested_iteration_reaches_the_discrete_solution():
+    """With a tight tolerance the nested iteration returns the solution of
+    S u = f on the target mesh (the same as PCG from zero)."""
+    from oracle import nested
+
+    J, K = 4, 4
+    g, u0 = synth.fourier_g(J, K, 5), synth.smooth_u0(K, 5)
+    u_ref, _, _ = oracle.solve(J, K, g, u0, tol=1e-13)
+    u, its, _ = nested.solve(J, K, g, u0, 1e-12, depth=3)
+    assert len(its) == 4
+    assert np.linalg.norm(u - u_ref) <= 1e-9 * np.linalg.norm(u_ref)
+
+
+@pytest.mark.slow
+def test_nested_iteration_error_tracks_the_discretisation_error():
+    """Section 4.2: with the algebraic tolerance proportional to the
+    discretisation error (0.1 h here), the nested iteration's error against
+    the exact solution exp(-2 pi^2 t) sin(pi x) sin(pi y) stays within 1 %
+    of the discrete solution's own error, with a few iterations per mesh."""
+    from oracle import nested
+
+    for L in (4, 5):
+        e_disc = _xnorm_error(L, L)
+        e_nest = _xnorm_error(L, L, lambda J, K, u0: nested.solve(J, K, None, u0, 0.1 * 2.0 ** -K, 3)[0])
+        assert e_nest <= 1.01 * e_disc, (L, e_nest, e_disc)
+        its = nested.solve(L, L, None, np.outer(*[np.sin(np.pi * np.arange(1, 2 ** L) / 2 ** L)] * 2),
+                           0.1 * 2.0 ** -L, 3)[1]
+        assert max(its) <= 8, its
