@@ -69,6 +69,17 @@ typedef struct {
   int max_outer;     /* STP_MIXED: refinement-step limit; 0 -> 20 */
   int graph;         /* replay each PCG iteration from a captured HIP graph:
                         0 (default) or 1 -> yes (not while profiling), -1 -> no */
+  int nested;        /* STP_FP64: nested iteration (Section 4.2) over up to this many
+                        coarser meshes (J - d, K - d), d = 1..min(nested, J, K - 1):
+                        the coarsest is solved from w = 0 to rel_tol * 2^d, every
+                        finer one from the coarser solution (coarse wavelet
+                        coefficients on the even time rows, P1 interpolation in
+                        space) to rel_tol * 2^d, the target mesh (d = 0) to rel_tol.
+                        The data of a coarser mesh are g and u0 at its nodes.  The
+                        stopping test stays relative to f-hat^T K_X f-hat of each
+                        mesh.  0 (default): off.  The coarser meshes are allocated
+                        with the context (at most 1/7 of its memory more; not
+                        counted by stp_footprint). */
 } stp_options;
 
 typedef struct {
@@ -82,6 +93,8 @@ typedef struct {
                             rounding (a relative error of a few 1e-3 at h = 2^-9) */
   double seconds;        /* device time of the solve (HIP events on the stream) */
   int status;            /* per right-hand side: STP_OK, STP_NOT_CONVERGED, STP_E_BREAKDOWN */
+  int coarse_iterations; /* nested iteration: S-hat applications on the coarser meshes,
+                            summed (0 without nesting) */
 } stp_stats;
 
 typedef struct stp_ctx stp_ctx;

@@ -35,13 +35,13 @@ STP_OP_W, STP_OP_WT, STP_OP_S, STP_OP_SHAT, STP_OP_KX, STP_OP_KSPACE, STP_OP_RHS
 class stp_options(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("vcycles", ctypes.c_int), ("sweeps", ctypes.c_int),
                 ("maxit", ctypes.c_int), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
-                ("graph", ctypes.c_int)]
+                ("graph", ctypes.c_int), ("nested", ctypes.c_int)]
 
 
 class stp_stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("outer_iterations", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("status", ctypes.c_int)]
+                ("status", ctypes.c_int), ("coarse_iterations", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

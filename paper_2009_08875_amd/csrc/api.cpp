@@ -45,6 +45,7 @@ stp_options resolve(const stp_options* o) {
   // inner_tol <= 0: chosen from the mesh in stp_create (default_inner_tol)
   if (r.max_outer <= 0) r.max_outer = 20;
   if (r.graph > 0) r.graph = 1;
+  if (r.nested < 0) r.nested = 0;
   return r;
 }
 
@@ -129,6 +130,7 @@ stp_status plan_context(Arena& ar, stp_ctx* c) {
   STP_TRY(ar.get(&c->fhat, vec));
   STP_TRY(ar.get(&c->u, vec));
   STP_TRY(ar.get(&c->sigma, c->rows));
+  STP_TRY(ar.get(&c->rhoref, c->nrhs));
   STP_TRY(ar.get(&c->partials, (int64_t)c->nrhs * std::max(1024, analysis_dot_blocks(c->K))));
   STP_TRY(ar.get(&c->tolv, c->nrhs));
   STP_TRY(ar.get(&c->sc.rho, c->nrhs));
@@ -160,6 +162,8 @@ stp_status plan_context(Arena& ar, stp_ctx* c) {
 }
 
 void free_all(stp_ctx* c) {
+  for (stp_ctx* n : c->nest) stp_destroy(n);
+  c->nest.clear();
   for (auto& t : c->timed) {
     c->ev_pool.push_back(t.a);
     c->ev_pool.push_back(t.b);
@@ -398,6 +402,25 @@ stp_status pcg_init(stp_ctx* c, PcgVecs<T>& v, const T* rhs, const double* tol) 
   return STP_OK;
 }
 
+// PCG start from the initial guess w = the coarse context's solution carried
+// to this mesh (nested iteration, Section 4.2): r = f-hat - S-hat w,
+// z = K_X r, rho = r^T z, p = z; the stopping test and rho0 refer to
+// f-hat^T K_X f-hat, the first residual's quantity from w = 0.  FP64.
+stp_status pcg_init_from(stp_ctx* c, const stp_ctx* coarse, const double* tol) {
+  PcgVecs<double>& v = c->pcg64;
+  Ops<double>& o = c->ops64;
+  HIP_TRY(prolong_w(c->stream, coarse->pcg64.w, v.w, c->J, c->K, c->nrhs));
+  STP_TRY(KX_apply<double>(c, o, c->fhat, v.z, c->nrhs));
+  HIP_TRY(dot<double>(c->stream, c->fhat, v.z, c->per_rhs, c->nrhs, c->partials, c->rhoref));
+  STP_TRY(Shat_apply<double>(c, o, v.w, v.q, c->nrhs));
+  HIP_TRY(residual64(c->stream, c->fhat, v.q, v.r, c->vec));
+  STP_TRY(KX_apply<double>(c, o, v.r, v.z, c->nrhs));
+  HIP_TRY(dot<double>(c->stream, v.r, v.z, c->per_rhs, c->nrhs, c->partials, c->sc.rhonew));
+  HIP_TRY(pcg_start(c->stream, c->sc, c->nrhs, tol, c->rhoref));
+  HIP_TRY(copy<double>(c->stream, v.z, v.p, c->vec));
+  return STP_OK;
+}
+
 // One PCG iteration for every right-hand side; inactive ones get gamma = 0
 // and keep w and r.  The direction update p = z + beta p of the previous
 // iteration happens at the start of this one (beta = 0 after the start, where
@@ -560,7 +583,7 @@ namespace stp {
 
 // First unit of a solve: f (Lemma 4.1), f-hat = W^T f, the PCG start.
 // `tol` holds one relative tolerance per right-hand side (host memory).
-stp_status drive_begin(stp_ctx* c, const double* tol) {
+stp_status drive_begin(stp_ctx* c, const double* tol, const stp_ctx* coarse) {
   const int nr = c->nrhs;
   for (int b = 0; b < nr; ++b) c->h_tol[b] = tol[b];
   c->solved = false;
@@ -569,7 +592,10 @@ stp_status drive_begin(stp_ctx* c, const double* tol) {
   STP_TRY(rhs_apply(c, c->fhat));
   HIP_TRY(wavelet<double>(c->stream, c->fhat, c->J, c->K, nr, false));
   if (c->prec == STP_FP64) {
-    STP_TRY(pcg_init<double>(c, c->pcg64, c->fhat, c->tolv));
+    if (coarse)
+      STP_TRY(pcg_init_from(c, coarse, c->tolv));
+    else
+      STP_TRY(pcg_init<double>(c, c->pcg64, c->fhat, c->tolv));
   } else {
     HIP_TRY(mixed_reset(c->stream, c->ms, nr));
     HIP_TRY(hipMemsetAsync(c->w64, 0, sizeof(double) * c->vec, c->stream));
@@ -749,6 +775,11 @@ stp_status stp_create(int J, int K, int nrhs, int precision, const stp_options* 
     set_error("the GPU kernels implement 3 Gauss-Seidel steps per grid (sweeps = 3)");
     return STP_E_UNSUPPORTED;
   }
+  if (o.nested > 0 && precision != STP_FP64) {
+    set_error("nested iteration is implemented for STP_FP64");
+    return STP_E_UNSUPPORTED;
+  }
+  const int depth = std::min(o.nested, std::min(J, K - 1));
   stp_ctx* c = new (std::nothrow) stp_ctx();
   if (!c) {
     set_error("host allocation failed");
@@ -785,8 +816,13 @@ stp_status stp_create(int J, int K, int nrhs, int precision, const stp_options* 
     stp_ctx probe;
     init_dims(&probe, J, K, nrhs, precision);
     size_t free_b = 0, total_b = 0;
-    if (plan_context(dry, &probe) == STP_OK && hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
-        dry.bytes > free_b) {
+    bool ok = plan_context(dry, &probe) == STP_OK;
+    for (int d = 1; ok && d <= depth; ++d) {
+      stp_ctx coarse;
+      init_dims(&coarse, J - d, K - d, nrhs, precision);
+      ok = plan_context(dry, &coarse) == STP_OK;
+    }
+    if (ok && hipMemGetInfo(&free_b, &total_b) == hipSuccess && dry.bytes > free_b) {
       set_error("context needs " + std::to_string(dry.bytes) + " bytes of device memory, " +
                 std::to_string(free_b) + " are free");
       return fail(STP_E_OUT_OF_MEMORY);
@@ -811,6 +847,15 @@ stp_status stp_create(int J, int K, int nrhs, int precision, const stp_options* 
       hipStreamSynchronize(c->stream) != hipSuccess) {
     set_error("initialisation kernels failed");
     return fail(STP_E_DEVICE);
+  }
+  // nested iteration: one context per coarser mesh, on this context's stream
+  for (int d = 1; d <= depth; ++d) {
+    stp_options oc = o;
+    oc.nested = 0;
+    stp_ctx* n = nullptr;
+    st = stp_create(J - d, K - d, nrhs, precision, &oc, c->stream, &n);
+    if (st < 0) return fail(st);
+    c->nest.push_back(n);
   }
   *out = c;
   return STP_OK;
@@ -863,19 +908,48 @@ stp_status stp_solve(stp_ctx* c, double rel_tol, stp_stats* per_rhs) {
     set_error("a solve is already in progress on this context");
     return STP_E_INVALID_ARG;
   }
-  std::vector<double> tol(c->nrhs, rel_tol);
-  auto run = [&]() -> stp_status {
-    STP_TRY(drive_begin(c, tol.data()));
-    while (c->drv.phase != stp_ctx::kDone) {
-      STP_TRY(drive_wait(c));
-      STP_TRY(drive_next(c));
+  auto run = [](stp_ctx* x, double t, const stp_ctx* coarse) -> stp_status {
+    std::vector<double> tol(x->nrhs, t);
+    STP_TRY(drive_begin(x, tol.data(), coarse));
+    while (x->drv.phase != stp_ctx::kDone) {
+      STP_TRY(drive_wait(x));
+      STP_TRY(drive_next(x));
     }
     return STP_OK;
   };
-  const stp_status st = run();
+  // nested iteration (Section 4.2): the coarsest mesh from zero, every finer
+  // mesh from the coarser solution, each to a tolerance that halves with
+  // the mesh width like the X-norm discretisation error
+  std::vector<int> coarse_its(c->nrhs, 0);
+  double coarse_seconds = 0.0;
+  stp_status st = STP_OK;
+  const int depth = (int)c->nest.size();
+  for (int d = depth; d >= 1 && st >= 0; --d) {
+    stp_ctx* n = c->nest[d - 1];
+    n->has_g = c->has_g;
+    if (hipSuccess != inject(c->stream, c->g, n->g, c->K, d, (int)c->rows_per, (int)n->rows_per,
+                             1 << d, c->nrhs) ||
+        hipSuccess != inject(c->stream, c->u0, n->u0, c->K, d, 1, 1, 1, c->nrhs)) {
+      set_error("nested iteration: injection of the data failed");
+      st = STP_E_DEVICE;
+      break;
+    }
+    st = run(n, rel_tol * std::ldexp(1.0, d), d < depth ? c->nest[d] : nullptr);
+    if (st < 0) {
+      n->drv.phase = stp_ctx::kIdle;
+      break;
+    }
+    for (int b = 0; b < c->nrhs; ++b) coarse_its[b] += n->stats[b].iterations;
+    coarse_seconds += n->stats[0].seconds;
+  }
+  if (st >= 0) st = run(c, rel_tol, depth > 0 ? c->nest[0] : nullptr);
   if (st < 0) {
     c->drv.phase = stp_ctx::kIdle;
     return st;
+  }
+  for (int b = 0; b < c->nrhs; ++b) {
+    c->stats[b].coarse_iterations = coarse_its[b];
+    c->stats[b].seconds += coarse_seconds;
   }
   stp_status worst = STP_OK;
   for (int b = 0; b < c->nrhs; ++b) {

@@ -116,7 +116,10 @@ struct PcgScalars {
 // start: rho = rho0 = rhonew, target = tol_b * sqrt(rho0) (tol: device array of
 // nrhs relative tolerances, or NULL for 0 = run to maxit), its = 0, active
 // unless rho0 == 0 (nothing to solve) or non-finite (breakdown).
-hipError_t pcg_start(hipStream_t s, PcgScalars sc, int nrhs, const double* tol);
+// ref (NULL: the first residual's rho): f-hat^T K_X f-hat per right-hand
+// side, the reference of the stopping test and of rho0 from an initial guess.
+hipError_t pcg_start(hipStream_t s, PcgScalars sc, int nrhs, const double* tol,
+                     const double* ref = nullptr);
 // gamma = rho / p^T q for active right-hand sides (breakdown if p^T q <= 0).
 hipError_t pcg_gamma(hipStream_t s, PcgScalars sc, int nrhs);
 // beta = rhonew / rho, rho = rhonew, its += 1, convergence test against target;
@@ -156,5 +159,16 @@ hipError_t add_correction(hipStream_t s, double* w, const float* d, int64_t n, i
                           const int* status);
 // sigma[b * (N+1) + i] = 2^row_level(i, J)
 hipError_t fill_level_sigma(hipStream_t s, double* sigma, int J, int nrhs);
+
+// ---- nested iteration (Section 4.2).
+// Data on a coarser mesh: dst (nrhs x rows_c slabs of level Kf - d) takes
+// the values of src (nrhs x rows_f slabs of level Kf) at its nodes: row i
+// from row i * tstride, node (a, b) from node (2^d a, 2^d b).
+hipError_t inject(hipStream_t s, const double* src, double* dst, int Kf, int d, int rows_f,
+                  int rows_c, int tstride, int nrhs);
+// wf (nrhs x (2^J + 1) slabs of level K) = the coefficients wc of mesh
+// (J - 1, K - 1) expressed on mesh (J, K): even rows from coarse rows by P1
+// interpolation in space, odd rows zero.
+hipError_t prolong_w(hipStream_t s, const double* wc, double* wf, int J, int K, int nrhs);
 
 }  // namespace stp

@@ -581,17 +581,21 @@ __global__ __launch_bounds__(kBlock) void update_p_kernel(T* __restrict__ p,
   p[k] = (T)((double)z[k] + bt * (double)p[k]);
 }
 
-__global__ void pcg_start_kernel(PcgScalars sc, int nrhs, const double* __restrict__ tol) {
+__global__ void pcg_start_kernel(PcgScalars sc, int nrhs, const double* __restrict__ tol,
+                                 const double* __restrict__ ref) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nrhs) return;
   const double rho = sc.rhonew[b];
   const double t = tol ? tol[b] : 0.0;
+  // the stopping test is relative to f-hat^T K_X f-hat: the first residual's
+  // quantity from w = 0, computed separately (ref) from an initial guess
+  const double r0 = ref ? ref[b] : rho;
   sc.rho[b] = rho;
-  sc.rho0[b] = rho;
+  sc.rho0[b] = r0;
   sc.its[b] = 0;
   sc.gamma[b] = 0.0;
   sc.beta[b] = 0.0;
-  sc.target[b] = t > 0.0 ? t * sqrt(rho) : 0.0;
+  sc.target[b] = t > 0.0 ? t * sqrt(fmax(r0, 0.0)) : 0.0;
   if (!isfinite(rho) || rho < 0.0) {
     sc.active[b] = 0;
     sc.status[b] = -3;
@@ -758,6 +762,65 @@ __global__ __launch_bounds__(kBlock) void add_correction_kernel(double* __restri
   if (i >= n || status[blockIdx.y] == -3) return;
   const int64_t k = (int64_t)blockIdx.y * n + i;
   w[k] += (double)d[k];
+}
+
+// Nested iteration: the data of a coarser mesh (level Kc = Kf - d in space)
+// are the values at its nodes, which are nodes of the fine mesh too: coarse
+// row i of right-hand side b is fine row i * tstride, coarse node (a, b) is
+// fine node (2^d a, 2^d b).  Pads are written zero.
+__global__ __launch_bounds__(kBlock) void inject_kernel(const double* __restrict__ src,
+                                                        double* __restrict__ dst, int Kf, int d,
+                                                        int rows_f, int rows_c, int tstride) {
+  const int Kc = Kf - d;
+  const int64_t slab_c = slab_elems(Kc);
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= slab_c) return;
+  const int row = blockIdx.y;  // coarse row within the right-hand side
+  const int b = blockIdx.z;
+  int gx, gy;
+  double v = 0.0;
+  if (node_of(idx, Kc, gx, gy)) {
+    const int64_t fr = (int64_t)b * rows_f + (int64_t)row * tstride;
+    v = src[fr * slab_elems(Kf) + (int64_t)((gy << d) - 1) * line_pitch(Kf) + ((gx << d) - 1)];
+  }
+  dst[((int64_t)b * rows_c + row) * slab_c + idx] = v;
+}
+
+// Nested iteration: wavelet-in-time, nodal-in-space coefficients of mesh
+// (J - 1, K - 1) carried to mesh (J, K).  The wavelets of the coarse mesh are
+// wavelets of the fine one: coarse row i moves to fine row 2 i and the odd
+// fine rows (the new finest level) are zero; in space the coarse P1 function
+// is interpolated at the fine nodes on the "/" mesh (Section 4, Section 4.2).
+__global__ __launch_bounds__(kBlock) void prolong_w_kernel(const double* __restrict__ wc,
+                                                           double* __restrict__ wf, int J,
+                                                           int K) {
+  const int64_t slab_f = slab_elems(K);
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= slab_f) return;
+  const int row = blockIdx.y;  // fine row within the right-hand side
+  const int b = blockIdx.z;
+  const int Nf = 1 << J;
+  double v = 0.0;
+  int gx, gy;
+  if ((row & 1) == 0 && node_of(idx, K, gx, gy)) {
+    const int nc = grid_n(K - 1), pc = line_pitch(K - 1);
+    const double* c =
+        wc + ((int64_t)b * ((Nf >> 1) + 1) + (row >> 1)) * slab_elems(K - 1);
+    // coarse value at coarse node (I, Jn), zero on the boundary
+    auto at = [&](int I, int Jn) {
+      return (I >= 1 && I <= nc && Jn >= 1 && Jn <= nc) ? c[(int64_t)(Jn - 1) * pc + (I - 1)] : 0.0;
+    };
+    const int I = gx >> 1, Jn = gy >> 1;
+    if (!(gx & 1) && !(gy & 1))
+      v = at(I, Jn);
+    else if ((gx & 1) && !(gy & 1))
+      v = 0.5 * (at(I, Jn) + at(I + 1, Jn));
+    else if (!(gx & 1) && (gy & 1))
+      v = 0.5 * (at(I, Jn) + at(I, Jn + 1));
+    else
+      v = 0.5 * (at(I, Jn) + at(I + 1, Jn + 1));
+  }
+  wf[((int64_t)b * (Nf + 1) + row) * slab_f + idx] = v;
 }
 
 __global__ void fill_level_sigma_kernel(double* sigma, int J, int nrhs) {
@@ -932,8 +995,8 @@ hipError_t update_p(hipStream_t s, T* p, const T* z, const double* beta, int64_t
   return hipGetLastError();
 }
 
-hipError_t pcg_start(hipStream_t s, PcgScalars sc, int nrhs, const double* tol) {
-  pcg_start_kernel<<<blocks_for(nrhs, 64), 64, 0, s>>>(sc, nrhs, tol);
+hipError_t pcg_start(hipStream_t s, PcgScalars sc, int nrhs, const double* tol, const double* ref) {
+  pcg_start_kernel<<<blocks_for(nrhs, 64), 64, 0, s>>>(sc, nrhs, tol, ref);
   return hipGetLastError();
 }
 hipError_t pcg_gamma(hipStream_t s, PcgScalars sc, int nrhs) {
@@ -987,6 +1050,19 @@ hipError_t mixed_adjust(hipStream_t s, PcgScalars sc, MixedState ms, int nrhs, c
 }
 hipError_t mixed_inner_done(hipStream_t s, PcgScalars sc, MixedState ms, int nrhs) {
   mixed_inner_done_kernel<<<blocks_for(nrhs, 64), 64, 0, s>>>(sc, ms, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t inject(hipStream_t s, const double* src, double* dst, int Kf, int d, int rows_f,
+                  int rows_c, int tstride, int nrhs) {
+  const dim3 grid(blocks_for(slab_elems(Kf - d)), rows_c, nrhs);
+  inject_kernel<<<grid, kBlock, 0, s>>>(src, dst, Kf, d, rows_f, rows_c, tstride);
+  return hipGetLastError();
+}
+
+hipError_t prolong_w(hipStream_t s, const double* wc, double* wf, int J, int K, int nrhs) {
+  const dim3 grid(blocks_for(slab_elems(K)), (1 << J) + 1, nrhs);
+  prolong_w_kernel<<<grid, kBlock, 0, s>>>(wc, wf, J, K);
   return hipGetLastError();
 }
 

@@ -83,6 +83,8 @@ struct stp_ctx {
   std::vector<stp_stats> stats;
 
   double* sigma = nullptr;  // 2^level per time row (K_X)
+  double* rhoref = nullptr; // f-hat^T K_X f-hat per right-hand side (PCG from an initial guess)
+  std::vector<stp_ctx*> nest;  // nested iteration: meshes (J - d, K - d), d = 1..nest.size()
   double* partials = nullptr;
   stp::PcgScalars sc{};
   stp::MixedState ms{};      // STP_MIXED only
@@ -138,7 +140,9 @@ namespace stp {
 // tolerances in host memory); drive_ready polls without blocking; drive_next
 // enqueues the next unit, and sets drv.phase = kDone (statistics in
 // ctx->stats, solution in ctx->u) after the last one.
-stp_status drive_begin(stp_ctx* c, const double* tol);
+// coarse (may be NULL): a context of mesh (J - 1, K - 1) whose last solve's
+// w, carried to this mesh, is the initial guess.
+stp_status drive_begin(stp_ctx* c, const double* tol, const stp_ctx* coarse = nullptr);
 bool drive_ready(stp_ctx* c);
 stp_status drive_wait(stp_ctx* c);
 stp_status drive_next(stp_ctx* c);
