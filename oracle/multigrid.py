@@ -29,16 +29,24 @@ import numpy as np
 from . import spatial
 
 
-def coefficients(a, sigma, h):
-    """Stencil of ``C = a A + sigma M`` on mesh width ``h``:
-    (centre, axis neighbour, diagonal neighbour)."""
+def coefficients(a, sigma, h, D=None, c=0.0):
+    """Stencil of ``C = a (A_D + c M) + sigma M`` on mesh width ``h`` (A_D the
+    stiffness of the diffusion tensor D, c the reaction coefficient of
+    Section 4): (centre, x-neighbours, y-neighbours, "/"-diagonal neighbours)."""
     m = h * h / 12.0
-    return 4.0 * a + 6.0 * m * sigma, -a + m * sigma, m * sigma
+    if D is None and c == 0.0:
+        return 4.0 * a + 6.0 * m * sigma, -a + m * sigma, -a + m * sigma, m * sigma
+    dxx, dyy, dxy = (1.0, 1.0, 0.0) if D is None else D
+    s = sigma + a * c
+    return (2.0 * a * (dxx + dyy - dxy) + 6.0 * m * s, a * (dxy - dxx) + m * s,
+            a * (dxy - dyy) + m * s, -a * dxy + m * s)
 
 
-def apply_C(x, a, sigma, h):
-    """``(a A_x + sigma M_x) x`` on a level with mesh width ``h``."""
-    return a * spatial.stiffness(x) + sigma * spatial.mass(x, h)
+def apply_C(x, a, sigma, h, D=None, c=0.0):
+    """``(a (A_D + c M_x) + sigma M_x) x`` on a level with mesh width ``h``."""
+    if D is None and c == 0.0:
+        return a * spatial.stiffness(x) + sigma * spatial.mass(x, h)
+    return a * spatial.stiffness(x, D) + (sigma + a * c) * spatial.mass(x, h)
 
 
 def colour_masks(n: int):
@@ -49,12 +57,15 @@ def colour_masks(n: int):
     return [c == 0, c == 1, c == 2]
 
 
-def relax_colour(x, b, a, sigma, h, mask):
+def relax_colour(x, b, a, sigma, h, mask, D=None, c=0.0):
     """One colour of Gauss-Seidel: every node in ``mask`` is set to
     ``(b - sum_nb C_nb x_nb) / C_centre`` using the current neighbour values."""
-    c0, c1, c2 = coefficients(a, sigma, h)
+    c0, cx, cy, c2 = coefficients(a, sigma, h, D, c)
     e, w, nth, s, ne, sw = spatial.neighbours(x)
-    off = c1 * (e + w + nth + s) + c2 * (ne + sw)
+    if D is None and c == 0.0:
+        off = cx * (e + w + nth + s) + c2 * (ne + sw)
+    else:
+        off = cx * (e + w) + cy * (nth + s) + c2 * (ne + sw)
     new = (b - off) / c0
     return np.where(mask, new, x)
 
@@ -92,30 +103,32 @@ def prolong(e):
     return out[..., 1:-1, 1:-1]
 
 
-def vcycle(level, b, x, a, sigma, sweeps=3):
+def vcycle(level, b, x, a, sigma, sweeps=3, D=None, c=0.0):
     """One V-cycle for ``C_level x = b`` from the initial guess ``x``."""
     h = 2.0 ** -level
     if level == 1:
-        c0, _, _ = coefficients(a, sigma, h)
+        c0 = coefficients(a, sigma, h, D, c)[0]
         return b / c0
     masks = colour_masks(b.shape[-1])
     for _ in range(sweeps):
-        for c in (0, 1, 2):
-            x = relax_colour(x, b, a, sigma, h, masks[c])
-    r = b - apply_C(x, a, sigma, h)
+        for col in (0, 1, 2):
+            x = relax_colour(x, b, a, sigma, h, masks[col], D, c)
+    r = b - apply_C(x, a, sigma, h, D, c)
     bc = restrict(r)
-    ec = vcycle(level - 1, bc, np.zeros_like(bc), a, sigma, sweeps)
+    ec = vcycle(level - 1, bc, np.zeros_like(bc), a, sigma, sweeps, D, c)
     x = x + prolong(ec)
     for _ in range(sweeps):
-        for c in (2, 1, 0):
-            x = relax_colour(x, b, a, sigma, h, masks[c])
+        for col in (2, 1, 0):
+            x = relax_colour(x, b, a, sigma, h, masks[col], D, c)
     return x
 
 
-def apply(b, K, a=1.0, sigma=0.0, cycles=2, sweeps=3):
-    """Multigrid approximation of ``(a A_x + sigma M_x)^{-1} b`` on level ``K``:
-    ``cycles`` V-cycles from zero.  ``b`` has shape ``(..., n, n)``; ``a`` and
-    ``sigma`` are scalars or arrays broadcasting against ``b[..., 0, 0]``."""
+def apply(b, K, a=1.0, sigma=0.0, cycles=2, sweeps=3, D=None, c=0.0):
+    """Multigrid approximation of ``(a (A_D + c M_x) + sigma M_x)^{-1} b`` on
+    level ``K``: ``cycles`` V-cycles from zero.  ``b`` has shape ``(..., n,
+    n)``; ``a`` and ``sigma`` are scalars or arrays broadcasting against
+    ``b[..., 0, 0]``; D (None: identity) and c are the diffusion tensor and
+    reaction coefficient of Section 4."""
     a = np.asarray(a, dtype=np.float64)
     sigma = np.asarray(sigma, dtype=np.float64)
     if a.ndim:
@@ -124,5 +137,5 @@ def apply(b, K, a=1.0, sigma=0.0, cycles=2, sweeps=3):
         sigma = sigma[..., None, None]
     x = np.zeros_like(b)
     for _ in range(cycles):
-        x = vcycle(K, b, x, a, sigma, sweeps)
+        x = vcycle(K, b, x, a, sigma, sweeps, D, c)
     return x

@@ -67,7 +67,7 @@ def levels(J: int, K: int, depth: int) -> int:
     return max(0, min(depth, J, K - 1))
 
 
-def solve(J, K, g, u0, tol, depth, maxit=200):
+def solve(J, K, g, u0, tol, depth, maxit=200, **kw):
     """Nested iteration on meshes (J - d, K - d), d = D..0 (D = levels(J, K,
     depth)).  Returns ``(u, iterations, history)``: the nodal solution on the
     target mesh, the PCG iterations per mesh (coarsest first), and the target
@@ -77,10 +77,10 @@ def solve(J, K, g, u0, tol, depth, maxit=200):
     its = []
     hist = []
     for d in range(D, -1, -1):
-        P = Problem(J - d, K - d)
+        P = Problem(J - d, K - d, **kw)
         gd = None if g is None else inject_g(g, J, K, d)
         fhat = P.WT(P.rhs(gd, inject_u0(u0, d)))
         w0 = None if w is None else prolong(w)
         w, k, hist = pcg(P, fhat, tol * 2.0 ** d, maxit, w0=w0)
         its.append(k)
-    return Problem(J, K).W(w), its, hist
+    return Problem(J, K, **kw).W(w), its, hist

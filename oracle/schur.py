@@ -19,9 +19,16 @@ class Problem:
     ``2**K x 2**K`` square mesh, with the multigrid parameters of Section 5.1
     (2 V-cycles, 3 smoothing steps, alpha = 0.3)."""
 
-    def __init__(self, J: int, K: int, alpha: float = ALPHA, cycles: int = 2, sweeps: int = 3):
+    def __init__(self, J: int, K: int, alpha: float = ALPHA, cycles: int = 2, sweeps: int = 3,
+                 D=None, c: float = 0.0):
         if J < 0 or K < 1:
             raise ValueError("need J >= 0 and K >= 1")
+        if D is not None and not (D[0] > 0 and D[1] > 0 and D[0] * D[1] > D[2] ** 2):
+            raise ValueError("D must be symmetric positive definite")
+        if c < 0:
+            raise ValueError("need c >= 0")
+        # reaction-diffusion operator of Section 4: A_x = A_D + c M_x
+        self.D, self.c = (None if D is None else tuple(float(v) for v in D)), float(c)
         self.J, self.K = J, K
         self.N = 2 ** J
         self.n = 2 ** K - 1
@@ -36,14 +43,17 @@ class Problem:
 
     # spatial operators on every row
     def A(self, x):
-        return spatial.stiffness(x)
+        """``A_x x``: diffusion (``D``, None = identity) plus reaction ``c M_x``."""
+        if self.D is None and self.c == 0.0:
+            return spatial.stiffness(x)
+        return spatial.stiffness(x, self.D) + self.c * spatial.mass(x, self.h)
 
     def M(self, x):
         return spatial.mass(x, self.h)
 
     def Kx(self, y):
         """``K_x ~ A_x^{-1}`` by multigrid on every row (Section 3.1)."""
-        return multigrid.apply(y, self.K, 1.0, 0.0, self.cycles, self.sweeps)
+        return multigrid.apply(y, self.K, 1.0, 0.0, self.cycles, self.sweeps, self.D, self.c)
 
     # Lemma 4.2
     def S(self, X):
@@ -83,9 +93,9 @@ class Problem:
         lev = wavelet.row_levels(self.J)
         sigma = 2.0 ** lev.astype(np.float64)
         a = self.alpha
-        Z = multigrid.apply(R, self.K, a, sigma, self.cycles, self.sweeps)
+        Z = multigrid.apply(R, self.K, a, sigma, self.cycles, self.sweeps, self.D, self.c)
         Z = self.A(Z)
-        return multigrid.apply(Z, self.K, a, sigma, self.cycles, self.sweeps)
+        return multigrid.apply(Z, self.K, a, sigma, self.cycles, self.sweeps, self.D, self.c)
 
     # Section 3.4, eq. (11)
     def W(self, w):

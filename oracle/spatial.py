@@ -9,7 +9,8 @@ continuous piecewise linears vanishing on the boundary (Section 4, Section
 Element integrals on this mesh (standard P1 on right triangles of area h^2/2):
 
   * stiffness ``A_x = <grad Phi_x, grad Phi_x>``: 4 at the node, -1 at the four
-    axis neighbours, 0 across the diagonal (independent of h in 2D);
+    axis neighbours, 0 across the diagonal (independent of h in 2D); with a
+    diffusion tensor D (Section 4) see :func:`stiffness`;
   * mass ``M_x = <Phi_x, Phi_x>``: h^2/2 at the node, h^2/12 at each of the six
     neighbours (i+-1, j), (i, j+-1), (i+1, j+1), (i-1, j-1).
 """
@@ -39,10 +40,21 @@ def neighbours(x: np.ndarray):
     return e, w, nth, s, ne, sw
 
 
-def stiffness(x: np.ndarray) -> np.ndarray:
-    """``A_x x``."""
-    e, w, nth, s, _, _ = neighbours(x)
-    return 4.0 * x - e - w - nth - s
+def stiffness(x: np.ndarray, D=None) -> np.ndarray:
+    """``A_x x`` for the diffusion of Section 4, ``int D grad u . grad v``, with
+    the constant symmetric positive definite ``D = [[dxx, dxy], [dxy, dyy]]``
+    given as ``(dxx, dyy, dxy)`` (None: the identity, the heat equation).
+
+    On the "/" mesh the P1 element integrals give, independently of h in 2D:
+    centre ``2 (dxx + dyy - dxy)``, the two x-neighbours ``dxy - dxx``, the two
+    y-neighbours ``dxy - dyy``, the two neighbours across the "/" diagonal
+    ``-dxy``; for D = Id the 5-point stencil (4, -1)."""
+    e, w, nth, s, ne, sw = neighbours(x)
+    if D is None:
+        return 4.0 * x - e - w - nth - s
+    dxx, dyy, dxy = D
+    return (2.0 * (dxx + dyy - dxy) * x + (dxy - dxx) * (e + w) + (dxy - dyy) * (nth + s)
+            - dxy * (ne + sw))
 
 
 def mass(x: np.ndarray, h: float) -> np.ndarray:

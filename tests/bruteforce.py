@@ -82,10 +82,12 @@ def legendre_test_space(N):
 
 # ------------------------------------------------------------ space, P1 FEM
 
-def p1_assembly(K):
-    """Stiffness and mass of P1 on the ``2**K x 2**K`` square mesh cut by "/"
+def p1_assembly(K, D=None):
+    """Stiffness (``int D grad u . grad v``, D = (dxx, dyy, dxy), None =
+    identity) and mass of P1 on the ``2**K x 2**K`` square mesh cut by "/"
     diagonals, assembled element by element; rows/columns are the interior
     nodes in order ``(j - 1) n + (i - 1)``."""
+    Dm = np.eye(2) if D is None else np.array([[D[0], D[2]], [D[2], D[1]]])
     m = 2 ** K
     h = 1.0 / m
     nn = m + 1
@@ -102,7 +104,7 @@ def p1_assembly(K):
                 P = np.array([[1.0, a * h, b * h] for a, b in tri])
                 area = 0.5 * abs(np.linalg.det(P))
                 G = np.linalg.inv(P)[1:, :]  # gradients of barycentric coordinates
-                Kloc = area * G.T @ G
+                Kloc = area * G.T @ Dm @ G
                 Mloc = area * Mloc_ref
                 ids = [gid(a, b) for a, b in tri]
                 for r in range(3):
@@ -141,12 +143,12 @@ def colour_of_nodes(K):
     return np.array([((i + 1) + (j + 1)) % 3 for j in range(n) for i in range(n)])
 
 
-def dense_vcycle_matrix_apply(b, x, K, a, sigma, ops, sweeps=3):
-    """One V-cycle written with dense matrices: Gauss-Seidel as a sequential
-    node-by-node loop visiting the colours in turn, explicit residual, ``P^T``
-    and ``P``."""
+def dense_vcycle_matrix_apply(b, x, K, a, sigma, ops, sweeps=3, react=0.0):
+    """One V-cycle written with dense matrices for ``a (A + c M) + sigma M``:
+    Gauss-Seidel as a sequential node-by-node loop visiting the colours in
+    turn, explicit residual, ``P^T`` and ``P``."""
     A, M = ops[K]
-    C = a * A + sigma * M
+    C = a * (A + react * M) + sigma * M
     if K == 1:
         return b / C[0, 0]
     col = colour_of_nodes(K)
@@ -159,7 +161,7 @@ def dense_vcycle_matrix_apply(b, x, K, a, sigma, ops, sweeps=3):
                 x[p] = (b[p] - (C[p] @ x - C[p, p] * x[p])) / C[p, p]
     P = ops[("P", K)]
     bc = P.T @ (b - C @ x)
-    ec = dense_vcycle_matrix_apply(bc, np.zeros_like(bc), K - 1, a, sigma, ops, sweeps)
+    ec = dense_vcycle_matrix_apply(bc, np.zeros_like(bc), K - 1, a, sigma, ops, sweeps, react)
     x = x + P @ ec
     for _ in range(sweeps):
         for c in order_f[::-1]:
@@ -169,27 +171,27 @@ def dense_vcycle_matrix_apply(b, x, K, a, sigma, ops, sweeps=3):
     return x
 
 
-def mg_ops(K):
+def mg_ops(K, D=None):
     ops = {}
     for k in range(1, K + 1):
-        ops[k] = p1_assembly(k)
+        ops[k] = p1_assembly(k, D)
         if k > 1:
             ops[("P", k)] = prolongation_by_evaluation(k)
     return ops
 
 
-def dense_mg(b, K, a, sigma, cycles=2, sweeps=3, ops=None):
-    ops = ops or mg_ops(K)
+def dense_mg(b, K, a, sigma, cycles=2, sweeps=3, ops=None, D=None, c=0.0):
+    ops = ops or mg_ops(K, D)
     x = np.zeros_like(b)
     for _ in range(cycles):
-        x = dense_vcycle_matrix_apply(b, x, K, a, sigma, ops, sweeps)
+        x = dense_vcycle_matrix_apply(b, x, K, a, sigma, ops, sweeps, c)
     return x
 
 
-def dense_mg_matrix(K, a, sigma, cycles=2, sweeps=3):
-    ops = mg_ops(K)
+def dense_mg_matrix(K, a, sigma, cycles=2, sweeps=3, D=None, c=0.0):
+    ops = mg_ops(K, D)
     n2 = (2 ** K - 1) ** 2
-    return np.stack([dense_mg(e, K, a, sigma, cycles, sweeps, ops) for e in np.eye(n2)], 1)
+    return np.stack([dense_mg(e, K, a, sigma, cycles, sweeps, ops, D, c) for e in np.eye(n2)], 1)
 
 
 # ------------------------------------------------------- wavelet by evaluation

@@ -76,8 +76,8 @@ def KX_rows(P: Problem, R, rows):
     rows = list(rows)
     sigma = 2.0 ** wavelet.row_levels(P.J)[rows].astype(np.float64)
     Z = multigrid.apply(np.asarray(R[rows], dtype=np.float64), P.K, P.alpha, sigma, P.cycles,
-                        P.sweeps)
-    return multigrid.apply(P.A(Z), P.K, P.alpha, sigma, P.cycles, P.sweeps)
+                        P.sweeps, P.D, P.c)
+    return multigrid.apply(P.A(Z), P.K, P.alpha, sigma, P.cycles, P.sweeps, P.D, P.c)
 
 
 def KX_first_factor(P: Problem, R, rows):
@@ -85,7 +85,7 @@ def KX_first_factor(P: Problem, R, rows):
     rows = list(rows)
     sigma = 2.0 ** wavelet.row_levels(P.J)[rows].astype(np.float64)
     return multigrid.apply(np.asarray(R[rows], dtype=np.float64), P.K, P.alpha, sigma, P.cycles,
-                           P.sweeps)
+                           P.sweeps, P.D, P.c)
 
 
 def W_columns(P: Problem, X, nodes):

@@ -175,11 +175,13 @@ def test_wavelets_have_vanishing_integral_and_levels():
 
 # ---------------------------------------------------------- Schur operator (O4)
 
-def _S_lemma41(J, K, Kx_dense):
-    """S = B^T K_Y B + Gamma_0 (x) M with an explicit Legendre Xi and O diagonal."""
+def _S_lemma41(J, K, Kx_dense, D=None, c=0.0):
+    """S = B^T K_Y B + Gamma_0 (x) M with an explicit Legendre Xi and O diagonal;
+    A = A_D + c M assembled element by element (Section 4)."""
     N = 2 ** J
     O, T, Nm = bf.legendre_test_space(N)
-    A, M = bf.p1_assembly(K)
+    A, M = bf.p1_assembly(K, D)
+    A = A + c * M
     B = np.kron(T, M) + np.kron(Nm, A)
     KY = np.kron(np.diag(1.0 / O), Kx_dense)
     G = np.zeros((N + 1, N + 1))
@@ -527,3 +529,116 @@ def test_nested_iteration_error_tracks_the_discretisation_error():
         its = nested.solve(L, L, None, np.outer(*[np.sin(np.pi * np.arange(1, 2 ** L) / 2 ** L)] * 2),
                            0.1 * 2.0 ** -L, 3)[1]
         assert max(its) <= 8, its
+
+
+# ------------------------------------- reaction-diffusion operator (Section 4)
+
+RD = [((2.0, 0.5, 0.3), 0.0), ((1.0, 3.0, -0.4), 5.0), (None, 7.0)]
+
+
+@pytest.mark.parametrize("D", [(2.0, 0.5, 0.3), (1.0, 3.0, -0.4), (0.7, 0.7, 0.6)])
+@pytest.mark.parametrize("K", [2, 3])
+def test_stiffness_with_diffusion_tensor_matches_assembly(D, K):
+    """int D grad u . grad v on the "/" mesh, element by element."""
+    A, _ = bf.p1_assembly(K, D)
+    n = 2 ** K - 1
+    got = op_matrix(lambda x: spatial.stiffness(x, D), (n, n))
+    assert np.allclose(got, A, rtol=0, atol=1e-13)
+
+
+def test_diagonal_diffusion_spectrum_closed_form():
+    """D = diag(dxx, dyy): eigenvalues 2 dxx (1 - cos p pi h) + 2 dyy (1 - cos q pi h)."""
+    K, D = 3, (2.0, 0.5, 0.0)
+    n, h = 2 ** K - 1, 2.0 ** -K
+    Am = op_matrix(lambda x: spatial.stiffness(x, D), (n, n))
+    p = np.arange(1, n + 1)
+    lam = np.sort((2 * D[0] * (1 - np.cos(p[:, None] * np.pi * h))
+                   + 2 * D[1] * (1 - np.cos(p[None, :] * np.pi * h))).ravel())
+    assert np.allclose(np.linalg.eigvalsh(Am), lam, atol=1e-12)
+
+
+@pytest.mark.parametrize("D,c", RD)
+@pytest.mark.parametrize("a,sigma", [(1.0, 0.0), (0.3, 16.0)])
+def test_multigrid_reaction_diffusion_matches_dense_vcycle(D, c, a, sigma):
+    """The multigrid for a (A_D + c M) + sigma M against the dense sequential
+    Gauss-Seidel V-cycle on element-assembled matrices."""
+    K = 3
+    b = np.random.default_rng(11).standard_normal((2 ** K - 1, 2 ** K - 1))
+    got = multigrid.apply(b, K, a, sigma, D=D, c=c)
+    ref = bf.dense_mg(b.ravel(), K, a, sigma, D=D, c=c)
+    assert np.allclose(got.ravel(), ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("D,c", RD)
+def test_S_lemma41_equals_lemma42_reaction_diffusion(D, c):
+    J, K = 2, 2
+    P = Problem(J, K, D=D, c=c)
+    Kx = op_matrix(P.Kx, (P.n, P.n))
+    _, _, S41, _, _ = _S_lemma41(J, K, Kx, D, c)
+    S42 = op_matrix(P.S, P.shape)
+    assert np.abs(S42 - S41).max() <= 1e-12 * np.abs(S41).max()
+    assert np.linalg.eigvalsh(0.5 * (S42 + S42.T)).min() > 0
+
+
+@pytest.mark.parametrize("D,c", RD)
+def test_S_closed_form_with_exact_inverse_reaction_diffusion(D, c):
+    """With K_x = A_x^{-1}, A_x = A_D + c M: the closed form of Lemma 4.2."""
+    J, K = 2, 2
+    P = Problem(J, K, D=D, c=c)
+    A, M = bf.p1_assembly(K, D)
+    A = A + c * M
+    Ainv = np.linalg.inv(A)
+    P.Kx = lambda y: (Ainv @ y.reshape(y.shape[0], -1).T).T.reshape(y.shape)
+    At, Mt, _ = bf.temporal_by_quadrature(2 ** J)
+    eN = np.zeros((2 ** J + 1, 2 ** J + 1))
+    eN[-1, -1] = 1.0
+    ref = np.kron(At, M @ Ainv @ M) + np.kron(Mt, A) + np.kron(eN, M)
+    got = op_matrix(P.S, P.shape)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("D,c", RD)
+def test_rhs_lemma41_reaction_diffusion(D, c):
+    J, K = 2, 2
+    P = Problem(J, K, D=D, c=c)
+    rng = np.random.default_rng(17)
+    g = rng.standard_normal(P.shape)
+    u0 = rng.standard_normal((P.n, P.n))
+    Kx = op_matrix(P.Kx, (P.n, P.n))
+    B, KY, _, A, M = _S_lemma41(J, K, Kx, D, c)
+    _, _, Nm = bf.legendre_test_space(2 ** J)
+    ref = B.T @ KY @ (np.kron(Nm, M) @ g.ravel())
+    ref[: P.n * P.n] += M @ u0.ravel()
+    got = P.rhs(g, u0).ravel()
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("D,c", RD)
+def test_pcg_matches_dense_solve_reaction_diffusion(D, c):
+    J, K = 3, 3
+    P = Problem(J, K, D=D, c=c)
+    g, u0 = synth.fourier_g(J, K, 8), synth.smooth_u0(K, 8)
+    S = op_matrix(P.S, P.shape)
+    exact = np.linalg.solve(S, P.rhs(g, u0).ravel())
+    u, its, _ = oracle.solve(J, K, g, u0, tol=1e-13, maxit=200, D=D, c=c)
+    assert np.linalg.norm(u.ravel() - exact) <= 1e-11 * np.linalg.norm(exact)
+    assert its < 40
+
+
+@pytest.mark.slow
+def test_reaction_diffusion_converges_to_exact_solution():
+    """u = exp(-((dxx + dyy) pi^2 + c) t) sin(pi x) sin(pi y) solves
+    u_t - div(D grad u) + c u = 0 for diagonal D; the nodal error of the
+    discrete solution falls by at least 1.8 per joint refinement of h and tau."""
+    D, c = (2.0, 0.5, 0.0), 3.0
+    rate = (D[0] + D[1]) * np.pi ** 2 + c
+    errs = []
+    for L in (3, 4, 5):
+        n = 2 ** L - 1
+        x = np.arange(1, n + 1) / 2 ** L
+        s = np.outer(np.sin(np.pi * x), np.sin(np.pi * x))
+        u, _, _ = oracle.solve(L, L, None, s, tol=1e-12, maxit=200, D=D, c=c)
+        t = np.arange(2 ** L + 1) / 2 ** L
+        exact = np.exp(-rate * t)[:, None, None] * s[None]
+        errs.append(np.abs(u - exact).max())
+    assert errs[0] / errs[1] >= 1.8 and errs[1] / errs[2] >= 1.8, errs
