@@ -80,6 +80,11 @@ typedef struct {
                         mesh.  0 (default): off.  The coarser meshes are allocated
                         with the context (at most 1/7 of its memory more; not
                         counted by stp_footprint). */
+  double diffusion[3];  /* the reaction-diffusion operator of Section 4,
+                           a(eta, zeta) = int D grad eta . grad zeta + c eta zeta:
+                           D = [[d0, d2], [d2, d1]], constant, symmetric positive
+                           definite (all three 0 -> identity, the heat equation) */
+  double reaction;      /* c >= 0 (0: no reaction term) */
 } stp_options;
 
 typedef struct {

@@ -35,7 +35,8 @@ STP_OP_W, STP_OP_WT, STP_OP_S, STP_OP_SHAT, STP_OP_KX, STP_OP_KSPACE, STP_OP_RHS
 class stp_options(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("vcycles", ctypes.c_int), ("sweeps", ctypes.c_int),
                 ("maxit", ctypes.c_int), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
-                ("graph", ctypes.c_int), ("nested", ctypes.c_int)]
+                ("graph", ctypes.c_int), ("nested", ctypes.c_int),
+                ("diffusion", ctypes.c_double * 3), ("reaction", ctypes.c_double)]
 
 
 class stp_stats(ctypes.Structure):
@@ -168,7 +169,10 @@ def _options(options):
         return None
     if isinstance(options, stp_options):
         return ctypes.byref(options)
-    o = stp_options(**options)
+    opts = dict(options)
+    if "diffusion" in opts:
+        opts["diffusion"] = (ctypes.c_double * 3)(*[float(v) for v in opts["diffusion"]])
+    o = stp_options(**opts)
     return ctypes.byref(o)
 
 

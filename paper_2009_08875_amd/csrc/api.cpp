@@ -46,6 +46,10 @@ stp_options resolve(const stp_options* o) {
   if (r.max_outer <= 0) r.max_outer = 20;
   if (r.graph > 0) r.graph = 1;
   if (r.nested < 0) r.nested = 0;
+  if (r.diffusion[0] == 0.0 && r.diffusion[1] == 0.0 && r.diffusion[2] == 0.0) {
+    r.diffusion[0] = 1.0;
+    r.diffusion[1] = 1.0;
+  }
   return r;
 }
 
@@ -258,7 +262,7 @@ stp_status mg_apply(stp_ctx* c, MgScratch<T>& mg, const T* b, T* x, int64_t rows
       for (int cyc = 0; cyc < c->opt.vcycles; ++cyc) {
         const bool last = cyc == c->opt.vcycles - 1;
         HIP_TRY(mg_coarse_cycle<T>(c->stream, cyc == 0 ? nullptr : xx, bb, xx, K, nr, a, sg,
-                                   write_Ax && last));
+                                   write_Ax && last, c->op));
       }
       continue;
     }
@@ -272,20 +276,21 @@ stp_status mg_apply(stp_ctx* c, MgScratch<T>& mg, const T* b, T* x, int64_t rows
       const T* xin = cyc == 0 ? nullptr : xx;
       const double pre_bytes = sizeof(T) * ((xin ? 3.0 : 2.0) * nodes + cnodes);
       STP_TRY(timed_launch(c, STP_KERNEL_MG_PRE, pre_bytes, [&] {
-        return mg_pre_stream<T>(c->stream, xin, bb, mg.xb[K], mg.b[K - 1], K, nr, a, sg);
+        return mg_pre_stream<T>(c->stream, xin, bb, mg.xb[K], mg.b[K - 1], K, nr, a, sg, c->op);
       }));
       for (int l = K - 1; l > kCoarseLevels; --l)
-        HIP_TRY(mg_pre_stream<T>(c->stream, nullptr, mg.b[l], mg.xb[l], mg.b[l - 1], l, nr, a, sg));
+        HIP_TRY(mg_pre_stream<T>(c->stream, nullptr, mg.b[l], mg.xb[l], mg.b[l - 1], l, nr, a, sg,
+                                 c->op));
       // levels kCoarseLevels .. 1 in one launch, from zero
       HIP_TRY(mg_coarse_cycle<T>(c->stream, nullptr, mg.b[kCoarseLevels], mg.xa[kCoarseLevels],
-                                 kCoarseLevels, nr, a, sg, false));
+                                 kCoarseLevels, nr, a, sg, false, c->op));
       for (int l = kCoarseLevels + 1; l <= K - 1; ++l)
         HIP_TRY(mg_post_stream<T>(c->stream, mg.xb[l], mg.b[l], mg.xa[l - 1], mg.xa[l], l, nr, a, sg,
-                                  false));
+                                  false, c->op));
       const double post_bytes = sizeof(T) * (3.0 * nodes + cnodes);
       STP_TRY(timed_launch(c, STP_KERNEL_MG_POST, post_bytes, [&] {
         return mg_post_stream<T>(c->stream, mg.xb[K], bb, mg.xa[K - 1], xx, K, nr, a, sg,
-                                 write_Ax && last);
+                                 write_Ax && last, c->op);
       }));
     }
   }
@@ -311,13 +316,13 @@ stp_status S_apply(stp_ctx* c, Ops<T>& o, const T* X, T* out, int nrhs) {
   T* z2 = o.z + v;
   // X in; y1, y2 out
   STP_TRY(timed_launch(c, STP_KERNEL_TIME_STENCIL, row_bytes<T>(c, rows, 3.0), [&] {
-    return time_stencil_pair<T>(c->stream, X, y1, y2, c->J, c->K, nrhs);
+    return time_stencil_pair<T>(c->stream, X, y1, y2, c->J, c->K, nrhs, c->op);
   }));
   // y1 | y2 and z1 | z2 are contiguous: one K_x application over both
   STP_TRY(mg_apply<T>(c, o.mg, y1, z1, 2 * rows, 1.0, nullptr));
   // z1, z2 in; S X out (row 0's M X_0 term is one row in 2^J + 1)
   STP_TRY(timed_launch(c, STP_KERNEL_COMBINE, row_bytes<T>(c, rows, 3.0), [&] {
-    return combine<T>(c->stream, z1, z2, X, c->per_rhs, out, c->J, c->K, nrhs);
+    return combine<T>(c->stream, z1, z2, X, c->per_rhs, out, c->J, c->K, nrhs, c->op);
   }));
   return STP_OK;
 }
@@ -375,7 +380,7 @@ stp_status rhs_apply(stp_ctx* c, double* f) {
   } else {
     HIP_TRY(hipMemsetAsync(z1, 0, sizeof(double) * 2 * v, c->stream));
   }
-  HIP_TRY(combine<double>(c->stream, z1, z2, c->u0, c->slab, f, c->J, c->K, c->nrhs));
+  HIP_TRY(combine<double>(c->stream, z1, z2, c->u0, c->slab, f, c->J, c->K, c->nrhs, c->op));
   return STP_OK;
 }
 
@@ -775,6 +780,12 @@ stp_status stp_create(int J, int K, int nrhs, int precision, const stp_options* 
     set_error("the GPU kernels implement 3 Gauss-Seidel steps per grid (sweeps = 3)");
     return STP_E_UNSUPPORTED;
   }
+  if (!(o.diffusion[0] > 0.0 && o.diffusion[1] > 0.0 &&
+        o.diffusion[0] * o.diffusion[1] > o.diffusion[2] * o.diffusion[2]) ||
+      !(o.reaction >= 0.0) || !std::isfinite(o.reaction)) {
+    set_error("the diffusion tensor must be symmetric positive definite and the reaction >= 0");
+    return STP_E_INVALID_ARG;
+  }
   if (o.nested > 0 && precision != STP_FP64) {
     set_error("nested iteration is implemented for STP_FP64");
     return STP_E_UNSUPPORTED;
@@ -787,6 +798,10 @@ stp_status stp_create(int J, int K, int nrhs, int precision, const stp_options* 
   }
   init_dims(c, J, K, nrhs, precision);
   c->opt = o;
+  c->op.dxx = o.diffusion[0];
+  c->op.dyy = o.diffusion[1];
+  c->op.dxy = o.diffusion[2];
+  c->op.c = o.reaction;
   if (c->opt.inner_tol <= 0.0) c->opt.inner_tol = default_inner_tol(K);
   c->use_graph = o.graph >= 0;
   c->has_g.assign(nrhs, 0);
@@ -1050,7 +1065,7 @@ stp_status apply_op_t(stp_ctx* c, int op, const double* in_dev, double* out_dev)
       STP_TRY(mg_apply<T>(c, o.mg, in_t, out_t, rows, 1.0, nullptr));
       break;
     case STP_OP_A:
-      HIP_TRY(apply_A<T>(c->stream, in_t, out_t, K, rows));
+      HIP_TRY(apply_A<T>(c->stream, in_t, out_t, K, rows, c->op));
       break;
     case STP_OP_M:
       HIP_TRY(apply_M<T>(c->stream, in_t, out_t, K, rows));

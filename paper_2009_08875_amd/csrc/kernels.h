@@ -12,6 +12,35 @@
 
 namespace stp {
 
+// ---- the spatial operator of Section 4: A_x = A_D + c M_x, the P1 stiffness
+// of int D grad u . grad v for the constant symmetric positive definite
+// D = [[dxx, dxy], [dxy, dyy]] plus the reaction c >= 0.  The heat equation
+// is D = Id, c = 0.
+struct SpaceOp {
+  double dxx = 1.0, dyy = 1.0, dxy = 0.0, c = 0.0;
+  __host__ __device__ bool heat() const {
+    return dxx == 1.0 && dyy == 1.0 && dxy == 0.0 && c == 0.0;
+  }
+};
+
+// Stencil of C = a A_x + sigma M_x on the level with mesh width 2^-l, on the
+// "/" mesh: centre, the x-neighbours (i +- 1, j), the y-neighbours
+// (i, j +- 1), the two neighbours across the "/" diagonal (i + 1, j + 1),
+// (i - 1, j - 1).  The element integrals of A_D: centre 2 (dxx + dyy - dxy),
+// x: dxy - dxx, y: dxy - dyy, diagonal: -dxy; of M_x: h^2/12 (6; 1 at each
+// of the six neighbours).
+struct Stencil {
+  double c0, cx, cy, cd;
+};
+__host__ __device__ inline Stencil stencil_of(const SpaceOp& op, double a, double sigma, int l) {
+  const double h = 1.0 / (double)(1 << l);
+  const double m = h * h / 12.0;
+  if (op.heat()) return {4.0 * a + 6.0 * m * sigma, -a + m * sigma, -a + m * sigma, m * sigma};
+  const double s = sigma + a * op.c;
+  return {2.0 * a * (op.dxx + op.dyy - op.dxy) + 6.0 * m * s, a * (op.dxy - op.dxx) + m * s,
+          a * (op.dxy - op.dyy) + m * s, -a * op.dxy + m * s};
+}
+
 // ---- multigrid for C = a A_x + sigma M_x on level l (Section 3.1, Theorem 3.1,
 // Section 5.1: 3 Gauss-Seidel steps per grid).  Arrays hold `rows` slabs of
 // level l (slab_elems(l) elements each); `sigma` has one value per row (NULL
@@ -23,13 +52,14 @@ namespace stp {
 // wavefront kernels (mg_stream.hip): rows held in registers, no halo along rows.
 template <typename T>
 hipError_t mg_pre_stream(hipStream_t s, const T* xin, const T* b, T* xout, T* bc, int l, int rows,
-                         double a, const double* sigma);
+                         double a, const double* sigma, const SpaceOp& op);
 // Coarse correction then backward smoothing: xout <- S_b^3(xin + P ec, b);
 // ec holds `rows` slabs of level l-1.  write_Ax: store A_x x (the stiffness
 // applied to the smoothed iterate) instead of x.
 template <typename T>
 hipError_t mg_post_stream(hipStream_t s, const T* xin, const T* b, const T* ec, T* xout, int l,
-                          int rows, double a, const double* sigma, bool write_Ax);
+                          int rows, double a, const double* sigma, bool write_Ax,
+                          const SpaceOp& op);
 
 // One V-cycle on levels L..1 (L <= kCoarseLevels) per row, each row in one
 // workgroup with all levels in LDS (mg_coarse.hip): xout = V(L, b, xin) (xin
@@ -37,7 +67,7 @@ hipError_t mg_post_stream(hipStream_t s, const T* xin, const T* b, const T* ec, 
 constexpr int kCoarseLevels = 5;
 template <typename T>
 hipError_t mg_coarse_cycle(hipStream_t s, const T* xin, const T* b, T* xout, int L, int rows,
-                           double a, const double* sigma, bool write_Ax);
+                           double a, const double* sigma, bool write_Ax, const SpaceOp& op);
 
 // ---- space-time stencils (Lemma 4.2 and Lemma 4.1, applied row-wise through
 // the Kronecker identity, eq. (15) of Section 5.2).  X has nrhs * (2^J+1) slabs
@@ -45,7 +75,8 @@ hipError_t mg_coarse_cycle(hipStream_t s, const T* xin, const T* b, T* xout, int
 
 // y1 = M (A_t X) + A (L^T X),  y2 = A (M_t X) + M (L X)   (first half of S).
 template <typename T>
-hipError_t time_stencil_pair(hipStream_t s, const T* X, T* y1, T* y2, int J, int K, int nrhs);
+hipError_t time_stencil_pair(hipStream_t s, const T* X, T* y1, T* y2, int J, int K, int nrhs,
+                             const SpaceOp& op);
 
 // G1 = M (L^T g),  G0 = M (M_t g)   (the data terms of f in Lemma 4.1).
 template <typename T>
@@ -55,11 +86,11 @@ hipError_t rhs_stencil_pair(hipStream_t s, const T* g, T* G1, T* G0, int J, int 
 // e_b = extra + b * extra_stride (one slab); extra == NULL adds nothing.
 template <typename T>
 hipError_t combine(hipStream_t s, const T* z1, const T* z2, const T* extra, int64_t extra_stride,
-                   T* out, int J, int K, int nrhs);
+                   T* out, int J, int K, int nrhs, const SpaceOp& op);
 
 // y = A_x x or y = M_x x on every one of `rows` slabs of level K.
 template <typename T>
-hipError_t apply_A(hipStream_t s, const T* x, T* y, int K, int rows);
+hipError_t apply_A(hipStream_t s, const T* x, T* y, int K, int rows, const SpaceOp& op);
 template <typename T>
 hipError_t apply_M(hipStream_t s, const T* x, T* y, int K, int rows);
 

@@ -56,9 +56,19 @@ __device__ inline T M_at(const T* s, int gx, int gy, int n, int pitch, T m12) {
                 at(s, gx, gy, 1, 1, n, pitch) + at(s, gx, gy, -1, -1, n, pitch));
 }
 
+// A_x = A_D + c M_x (Section 4) at node (gx, gy), with the stencil of
+// stencil_of(op, 1, 0, K).
+template <typename T>
+__device__ inline T Aop_at(const T* s, int gx, int gy, int n, int pitch, const Stencil& st) {
+  return ((T(st.c0) * at(s, gx, gy, 0, 0, n, pitch) +
+           T(st.cx) * (at(s, gx, gy, 1, 0, n, pitch) + at(s, gx, gy, -1, 0, n, pitch))) +
+          T(st.cy) * (at(s, gx, gy, 0, 1, n, pitch) + at(s, gx, gy, 0, -1, n, pitch))) +
+         T(st.cd) * (at(s, gx, gy, 1, 1, n, pitch) + at(s, gx, gy, -1, -1, n, pitch));
+}
+
 template <typename T, bool IS_A>
 __global__ __launch_bounds__(kBlock) void apply_AM_kernel(const T* __restrict__ x,
-                                                          T* __restrict__ y, int K) {
+                                                          T* __restrict__ y, int K, SpaceOp op) {
   const int64_t slab = slab_elems(K);
   const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (idx >= slab) return;
@@ -71,8 +81,12 @@ __global__ __launch_bounds__(kBlock) void apply_AM_kernel(const T* __restrict__ 
   const int n = grid_n(K), pitch = line_pitch(K);
   const double h = 1.0 / (double)(1 << K);
   const T m12 = T(h * h / 12.0);
-  y[row * slab + idx] = IS_A ? A_at(x + row * slab, gx, gy, n, pitch)
-                             : M_at(x + row * slab, gx, gy, n, pitch, m12);
+  if constexpr (IS_A) {
+    y[row * slab + idx] = op.heat() ? A_at(x + row * slab, gx, gy, n, pitch)
+                                    : Aop_at(x + row * slab, gx, gy, n, pitch, stencil_of(op, 1.0, 0.0, K));
+  } else {
+    y[row * slab + idx] = M_at(x + row * slab, gx, gy, n, pitch, m12);
+  }
 }
 
 // ------------------------------------------------------------------ wavelet
@@ -836,14 +850,15 @@ __global__ void fill_level_sigma_kernel(double* sigma, int J, int nrhs) {
 // ================================================================ launchers
 
 template <typename T>
-hipError_t apply_A(hipStream_t s, const T* x, T* y, int K, int rows) {
-  apply_AM_kernel<T, true><<<dim3(blocks_for(slab_elems(K)), rows), kBlock, 0, s>>>(x, y, K);
+hipError_t apply_A(hipStream_t s, const T* x, T* y, int K, int rows, const SpaceOp& op) {
+  apply_AM_kernel<T, true><<<dim3(blocks_for(slab_elems(K)), rows), kBlock, 0, s>>>(x, y, K, op);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t apply_M(hipStream_t s, const T* x, T* y, int K, int rows) {
-  apply_AM_kernel<T, false><<<dim3(blocks_for(slab_elems(K)), rows), kBlock, 0, s>>>(x, y, K);
+  apply_AM_kernel<T, false><<<dim3(blocks_for(slab_elems(K)), rows), kBlock, 0, s>>>(x, y, K,
+                                                                                     SpaceOp{});
   return hipGetLastError();
 }
 
@@ -1074,7 +1089,7 @@ hipError_t fill_level_sigma(hipStream_t s, double* sigma, int J, int nrhs) {
 
 // ---------------------------------------------------------- instantiations
 #define STP_INSTANTIATE(T)                                                                        \
-  template hipError_t apply_A<T>(hipStream_t, const T*, T*, int, int);                            \
+  template hipError_t apply_A<T>(hipStream_t, const T*, T*, int, int, const SpaceOp&);            \
   template hipError_t apply_M<T>(hipStream_t, const T*, T*, int, int);                            \
   template hipError_t wavelet<T>(hipStream_t, T*, int, int, int, bool);                           \
   template hipError_t synthesis<T>(hipStream_t, const T*, T*, int, int, int);                     \

@@ -23,21 +23,35 @@ namespace {
 
 
 struct LevelCoef {
-  double c0, c1, c2;  // centre, axis neighbours, the two "/" diagonal neighbours
+  double c0, cx, cy, c2;  // centre, x- and y-neighbours, the two "/" diagonal neighbours
   double inv_c0;
+  bool iso;               // cx == cy: the four axis neighbours share one coefficient
 };
 
-__device__ __forceinline__ LevelCoef level_coef(double a, double sigma, int l) {
-  const double h = 1.0 / (double)(1 << l);
-  const double m = h * h / 12.0;
-  const double c0 = 4.0 * a + 6.0 * m * sigma;
-  return {c0, -a + m * sigma, m * sigma, 1.0 / c0};
+__device__ __forceinline__ LevelCoef level_coef(double a, double sigma, int l, const SpaceOp& op) {
+  const Stencil st = stencil_of(op, a, sigma, l);
+  return {st.c0, st.cx, st.cy, st.cd, 1.0 / st.c0, st.cx == st.cy};
 }
+
+
 
 // Compact n x n arrays in LDS; node (i, j), 1-based, at (j - 1) n + (i - 1).
 template <typename T>
 __device__ __forceinline__ T at(const T* v, int n, int i, int j) {
   return (i >= 1 && i <= n && j >= 1 && j <= n) ? v[(j - 1) * n + (i - 1)] : T(0);
+}
+
+// sum_nb C_nb x_nb at node (i, j) (the off-centre part of the stencil)
+template <typename T>
+__device__ __forceinline__ T off_centre(const T* x, int n, int i, int j, const LevelCoef& cf) {
+  const T diag = T(cf.c2) * (at(x, n, i + 1, j + 1) + at(x, n, i - 1, j - 1));
+  if (cf.iso)
+    return T(cf.cx) * (((at(x, n, i + 1, j) + at(x, n, i - 1, j)) + at(x, n, i, j + 1)) +
+                       at(x, n, i, j - 1)) +
+           diag;
+  return (T(cf.cx) * (at(x, n, i + 1, j) + at(x, n, i - 1, j)) +
+          T(cf.cy) * (at(x, n, i, j + 1) + at(x, n, i, j - 1))) +
+         diag;
 }
 
 // One colour of Gauss-Seidel: every node (i, j) with (i + j) mod 3 == colour
@@ -52,9 +66,7 @@ __device__ void relax(T* x, const T* b, int n, int colour, const LevelCoef& cf) 
     if (i == 0) i = 3;
     i += 3 * (k % m);
     if (i > n) continue;
-    const T off = T(cf.c1) * (((at(x, n, i + 1, j) + at(x, n, i - 1, j)) + at(x, n, i, j + 1)) +
-                              at(x, n, i, j - 1)) +
-                  T(cf.c2) * (at(x, n, i + 1, j + 1) + at(x, n, i - 1, j - 1));
+    const T off = off_centre(x, n, i, j, cf);
     x[(j - 1) * n + (i - 1)] = (b[(j - 1) * n + (i - 1)] - off) * T(cf.inv_c0);
   }
 }
@@ -74,7 +86,7 @@ template <typename T, int NT>
 __global__ __launch_bounds__(NT) void mg_coarse_kernel(const T* xin, const T* b, T* xout,
                                                              int L, double a,
                                                              const double* __restrict__ sigma,
-                                                             int write_Ax) {
+                                                             int write_Ax, SpaceOp op) {
   extern __shared__ unsigned char smem[];
   T* sh = reinterpret_cast<T*>(smem);
   // LDS: x_l and b_l for l = L..1, then a residual array of level L
@@ -98,7 +110,7 @@ __global__ __launch_bounds__(NT) void mg_coarse_kernel(const T* xin, const T* b,
   __syncthreads();
   // down: smooth, residual, restrict
   for (int l = L; l >= 2; --l) {
-    const LevelCoef cf = level_coef(a, sg, l);
+    const LevelCoef cf = level_coef(a, sg, l, op);
     T* x = sh + off_x(l);
     const T* bl = sh + off_b(l);
     const int nn = nl(l);
@@ -109,10 +121,7 @@ __global__ __launch_bounds__(NT) void mg_coarse_kernel(const T* xin, const T* b,
     sweeps<NT>(x, bl, nn, cf, true);
     for (int k = threadIdx.x; k < nn * nn; k += NT) {
       const int i = k % nn + 1, j = k / nn + 1;
-      const T cx = T(cf.c0) * x[k] +
-                   T(cf.c1) * (((at(x, nn, i + 1, j) + at(x, nn, i - 1, j)) + at(x, nn, i, j + 1)) +
-                               at(x, nn, i, j - 1)) +
-                   T(cf.c2) * (at(x, nn, i + 1, j + 1) + at(x, nn, i - 1, j - 1));
+      const T cx = T(cf.c0) * x[k] + off_centre(x, nn, i, j, cf);
       r[k] = bl[k] - cx;
     }
     __syncthreads();
@@ -130,11 +139,11 @@ __global__ __launch_bounds__(NT) void mg_coarse_kernel(const T* xin, const T* b,
     __syncthreads();
   }
   // the one-node grid (h = 1/2)
-  if (threadIdx.x == 0) sh[off_x(1)] = sh[off_b(1)] * T(level_coef(a, sg, 1).inv_c0);
+  if (threadIdx.x == 0) sh[off_x(1)] = sh[off_b(1)] * T(level_coef(a, sg, 1, op).inv_c0);
   __syncthreads();
   // up: prolongate the correction, smooth backwards
   for (int l = 2; l <= L; ++l) {
-    const LevelCoef cf = level_coef(a, sg, l);
+    const LevelCoef cf = level_coef(a, sg, l, op);
     T* x = sh + off_x(l);
     const T* e = sh + off_x(l - 1);
     const int nn = nl(l), mc = nl(l - 1);
@@ -156,12 +165,18 @@ __global__ __launch_bounds__(NT) void mg_coarse_kernel(const T* xin, const T* b,
     sweeps<NT>(x, sh + off_b(l), nn, cf, false);
   }
   const T* x = sh + off_x(L);
+  const bool heat = op.heat();
+  const LevelCoef ac = level_coef(1.0, 0.0, L, op);  // A_x itself (Section 4)
   for (int k = threadIdx.x; k < n * n; k += NT) {
     const int i = k % n + 1, j = k / n + 1;
     T v = x[k];
-    if (write_Ax)
-      v = (((T(4) * v - at(x, n, i + 1, j)) - at(x, n, i - 1, j)) - at(x, n, i, j + 1)) -
-          at(x, n, i, j - 1);
+    if (write_Ax) {
+      if (heat)
+        v = (((T(4) * v - at(x, n, i + 1, j)) - at(x, n, i - 1, j)) - at(x, n, i, j + 1)) -
+            at(x, n, i, j - 1);
+      else
+        v = T(ac.c0) * v + off_centre(x, n, i, j, ac);
+    }
     xout[base + (int64_t)(j - 1) * pitch + (i - 1)] = v;
   }
 }
@@ -177,18 +192,18 @@ size_t mg_coarse_lds_bytes(int L, size_t elem) {
 
 template <typename T>
 hipError_t mg_coarse_cycle(hipStream_t s, const T* xin, const T* b, T* xout, int L, int rows,
-                           double a, const double* sigma, bool write_Ax) {
+                           double a, const double* sigma, bool write_Ax, const SpaceOp& op) {
   if (L < 1 || L > kCoarseLevels) return hipErrorInvalidValue;
   const size_t lds = mg_coarse_lds_bytes(L, sizeof(T));
   // workgroups of 2, 4 or 8 waves per time row (tuned per level and row count)
   auto go = [&](int c) -> hipError_t {
     const int wa = write_Ax ? 1 : 0;
     if (c == 0)
-      mg_coarse_kernel<T, 256><<<rows, 256, lds, s>>>(xin, b, xout, L, a, sigma, wa);
+      mg_coarse_kernel<T, 256><<<rows, 256, lds, s>>>(xin, b, xout, L, a, sigma, wa, op);
     else if (c == 1)
-      mg_coarse_kernel<T, 128><<<rows, 128, lds, s>>>(xin, b, xout, L, a, sigma, wa);
+      mg_coarse_kernel<T, 128><<<rows, 128, lds, s>>>(xin, b, xout, L, a, sigma, wa, op);
     else
-      mg_coarse_kernel<T, 512><<<rows, 512, lds, s>>>(xin, b, xout, L, a, sigma, wa);
+      mg_coarse_kernel<T, 512><<<rows, 512, lds, s>>>(xin, b, xout, L, a, sigma, wa, op);
     return hipGetLastError();
   };
   const uint64_t key = tune_key(3, sizeof(T), (uint64_t)L, (uint64_t)rows);
@@ -199,8 +214,9 @@ hipError_t mg_coarse_cycle(hipStream_t s, const T* xin, const T* b, T* xout, int
 }
 
 template hipError_t mg_coarse_cycle<double>(hipStream_t, const double*, const double*, double*,
-                                            int, int, double, const double*, bool);
+                                            int, int, double, const double*, bool,
+                                            const SpaceOp&);
 template hipError_t mg_coarse_cycle<float>(hipStream_t, const float*, const float*, float*, int,
-                                           int, double, const double*, bool);
+                                           int, double, const double*, bool, const SpaceOp&);
 
 }  // namespace stp

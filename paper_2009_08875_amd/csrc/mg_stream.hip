@@ -215,13 +215,19 @@ struct Args {
   bool out[3];  // column written by this strip
   int gx[3];
   // The right-hand side is stored scaled by 1 / centre, b' = b / c0, and the
-  // update reads x = b' - q1 (E + W + N + S) - q2 (NE + SW) with q = c / c0,
-  // one fused multiply-add per neighbour; q1, q2 are zero outside the grid so
-  // those columns stay exactly zero.
-  T q1[3];
+  // update reads x = b' - qx (E + W) - qy (N + S) - q2 (NE + SW) with
+  // q = c / c0, one fused multiply-add per neighbour; the q are zero outside
+  // the grid so those columns stay exactly zero.  qx = qy unless the
+  // diffusion tensor is anisotropic (Section 4).
+  T qx[3];
+  T qy[3];
   T q2[3];
   T cinv;       // 1 / c0 (scales b when it enters the window)
   T c0;
+  // A_x itself (the fused A x output): heat equation (5 points, -1 and 4) or
+  // the stencil of A_D + c M (centre, x, y, "/" diagonal)
+  bool heat;
+  T a0, ax, ay, ad;
   int lo, hi;   // output columns of this strip
   int cI0;      // pre: first coarse column of the strip, (gxs + 1) / 2
   bool gx0_even;
@@ -230,7 +236,7 @@ struct Args {
 // One Gauss-Seidel update of the column with in-lane index K in the row held
 // in slot SR (neighbour rows in slots SN above, SS below); t is its scaled
 // right-hand side b / c0.  Columns outside
-// the grid have cinv = q1 = q2 = 0 and b = 0, so they stay exactly zero.
+// the grid have cinv = qx = qy = q2 = 0 and b = 0, so they stay exactly zero.
 // FWD: the value written by the previous phase is the north-east neighbour
 // (it only matters with the mass term, DIAG); backward: the north neighbour.
 template <typename T, bool FWD, bool DIAG, int K, int SR, int SN, int SS>
@@ -251,13 +257,13 @@ __device__ __forceinline__ void relax(State<T>& st, const Args<T>& A, T t) {
     if constexpr (DIAG) xsw = from_left(st.x[SS][2]);
   }
   const T xn = st.x[SN][K], xs = st.x[SS][K];
-  const T m1 = -A.q1[K], m2 = -A.q2[K];
+  const T m1 = -A.qx[K], m1y = -A.qy[K], m2 = -A.q2[K];
   if constexpr (FWD) {
     // the north-east neighbour was written by the previous phase: it goes last
     t = fma(m1, xe, t);
     t = fma(m1, xw, t);
-    t = fma(m1, xn, t);
-    t = fma(m1, xs, t);
+    t = fma(m1y, xn, t);
+    t = fma(m1y, xs, t);
     if constexpr (DIAG) {
       t = fma(m2, xsw, t);
       t = fma(m2, xne, t);
@@ -266,12 +272,12 @@ __device__ __forceinline__ void relax(State<T>& st, const Args<T>& A, T t) {
     // the north neighbour was written by the previous phase: it goes last
     t = fma(m1, xe, t);
     t = fma(m1, xw, t);
-    t = fma(m1, xs, t);
+    t = fma(m1y, xs, t);
     if constexpr (DIAG) {
       t = fma(m2, xne, t);
       t = fma(m2, xsw, t);
     }
-    t = fma(m1, xn, t);
+    t = fma(m1y, xn, t);
   }
   st.x[SR][K] = t;
 }
@@ -291,11 +297,11 @@ __device__ __forceinline__ void residual(State<T>& st, const Args<T>& A) {
     const T xe = K < 2 ? st.x[SR][K < 2 ? K + 1 : 0] : e2;
     const T xw = K > 0 ? st.x[SR][K > 0 ? K - 1 : 0] : w0;
     T t = bget<T, SR, K>(st) - st.x[SR][K];
-    const T m1 = -A.q1[K];
+    const T m1 = -A.qx[K], m1y = -A.qy[K];
     t = fma(m1, xe, t);
     t = fma(m1, xw, t);
-    t = fma(m1, st.x[SN][K], t);
-    t = fma(m1, st.x[SS][K], t);
+    t = fma(m1y, st.x[SN][K], t);
+    t = fma(m1y, st.x[SS][K], t);
     if constexpr (DIAG) {
       const T xne = K < 2 ? st.x[SN][K < 2 ? K + 1 : 0] : ne2;
       const T xsw = K > 0 ? st.x[SS][K > 0 ? K - 1 : 0] : sw0;
@@ -466,12 +472,28 @@ __device__ __forceinline__ void step(State<T>& st, const Args<T>& A, int s0) {
     const T e2 = from_right(st.x[SR][0]);
     const T w0 = from_left(st.x[SR][2]);
     const int lane = threadIdx.x & 63;
-    static_for<0, 3>([&](auto KK) {
-      constexpr int K = decltype(KK)::value;
-      const T xe = K < 2 ? st.x[SR][K < 2 ? K + 1 : 0] : e2;
-      const T xw = K > 0 ? st.x[SR][K > 0 ? K - 1 : 0] : w0;
-      st.stg[K * 64 + lane] = (((T(4) * st.x[SR][K] - xe) - xw) - st.x[SN][K]) - st.x[SS][K];
-    });
+    if (A.heat) {
+      static_for<0, 3>([&](auto KK) {
+        constexpr int K = decltype(KK)::value;
+        const T xe = K < 2 ? st.x[SR][K < 2 ? K + 1 : 0] : e2;
+        const T xw = K > 0 ? st.x[SR][K > 0 ? K - 1 : 0] : w0;
+        st.stg[K * 64 + lane] = (((T(4) * st.x[SR][K] - xe) - xw) - st.x[SN][K]) - st.x[SS][K];
+      });
+    } else {
+      // A_D + c M (Section 4): the 7-point stencil, "/" neighbours included
+      const T ne2 = from_right(st.x[SN][0]);
+      const T sw0 = from_left(st.x[SS][2]);
+      static_for<0, 3>([&](auto KK) {
+        constexpr int K = decltype(KK)::value;
+        const T xe = K < 2 ? st.x[SR][K < 2 ? K + 1 : 0] : e2;
+        const T xw = K > 0 ? st.x[SR][K > 0 ? K - 1 : 0] : w0;
+        const T xne = K < 2 ? st.x[SN][K < 2 ? K + 1 : 0] : ne2;
+        const T xsw = K > 0 ? st.x[SS][K > 0 ? K - 1 : 0] : sw0;
+        st.stg[K * 64 + lane] = ((A.a0 * st.x[SR][K] + A.ax * (xe + xw)) +
+                                 A.ay * (st.x[SN][K] + st.x[SS][K])) +
+                                A.ad * (xne + xsw);
+      });
+    }
     const bool ok = r >= A.ys && r <= A.ye;
     const int64_t ro = A.off + (int64_t)(ok ? r - 1 : 0) * A.pitch + (A.lo - 1);
     const Rsrc rs = rsrc(A.xout + ro, ok ? (uint32_t)((A.hi - A.lo + 1) * sizeof(T)) : 0u);
@@ -545,7 +567,7 @@ __device__ __forceinline__ void run_segment(const T* __restrict__ xin, const T* 
                                             const T* __restrict__ ec, T* __restrict__ xout,
                                             T* __restrict__ bc, int l, int row, int strip, int ys,
                                             int ye, double a, const double* __restrict__ sigma,
-                                            T* bwin, T* stg) {
+                                            const SpaceOp& op, T* bwin, T* stg) {
   const int lane = threadIdx.x & 63;
   constexpr int H = PRE ? kHaloPre : (WRITE_A ? kHaloPostA : kHaloPost);
   Args<T> A;
@@ -566,20 +588,27 @@ __device__ __forceinline__ void run_segment(const T* __restrict__ xin, const T* 
   strip_geometry(strip, A.n, H, gxs, lo, hi);
 
   const double sg = sigma ? sigma[row] : 0.0;
-  const double h = 1.0 / (double)(1 << l);
-  const double m = h * h / 12.0;
-  const double c0d = 4.0 * a + 6.0 * m * sg;
-  const double c1d = -a + m * sg, c2d = m * sg;
+  const Stencil sc = stencil_of(op, a, sg, l);
+  const double c0d = sc.c0;
   A.c0 = (T)c0d;
   A.cinv = (T)(1.0 / c0d);
+  A.heat = op.heat();
+  {
+    const Stencil as = stencil_of(op, 1.0, 0.0, l);
+    A.a0 = (T)as.c0;
+    A.ax = (T)as.cx;
+    A.ay = (T)as.cy;
+    A.ad = (T)as.cd;
+  }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int gx = gxs + 3 * lane + k;
     A.gx[k] = gx;
     A.in[k] = gx >= 1 && gx <= A.n;
     A.out[k] = gx >= lo && gx <= hi;
-    A.q1[k] = A.in[k] ? (T)(c1d / c0d) : T(0);
-    A.q2[k] = A.in[k] ? (T)(c2d / c0d) : T(0);
+    A.qx[k] = A.in[k] ? (T)(sc.cx / c0d) : T(0);
+    A.qy[k] = A.in[k] ? (T)(sc.cy / c0d) : T(0);
+    A.q2[k] = A.in[k] ? (T)(sc.cd / c0d) : T(0);
     A.kld[k] = (gx - 1) * (int)sizeof(T);
   }
   A.lo = lo;
@@ -662,7 +691,7 @@ template <typename T, bool PRE, bool XIN, bool DIAG, bool WRITE_A>
 __global__ __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(2))) void mg_stream_kernel(
     const T* __restrict__ xin, const T* __restrict__ b, const T* __restrict__ ec,
     T* __restrict__ xout, T* __restrict__ bc, int l, int nstrips, int rows, int groups, double a,
-    const double* __restrict__ sigma) {
+    const double* __restrict__ sigma, SpaceOp op) {
   __shared__ T bwin[kWavesPerBlock][kWin * 3 * 64];
   __shared__ T stg[kWavesPerBlock][kStripCols];
   // the wave index is uniform across the wave: say so, so that every row and
@@ -681,7 +710,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_pe
     const int64_t rend = (int64_t)(row + 1) * n;
     const int ye = (int)((ub < rend ? ub : rend) - (int64_t)row * n);
     run_segment<T, PRE, XIN, DIAG, WRITE_A>(xin, b, ec, xout, bc, l, row, strip, ys, ye, a,
-                                            sigma, bwin[threadIdx.x >> 6], stg[threadIdx.x >> 6]);
+                                            sigma, op, bwin[threadIdx.x >> 6],
+                                            stg[threadIdx.x >> 6]);
     u = (int64_t)row * n + ye;
   }
 }
@@ -703,7 +733,7 @@ int resident_waves(K kernel) {
 
 template <typename T, bool PRE, bool XIN, bool DIAG, bool WRITE_A>
 hipError_t launch(hipStream_t s, const T* xin, const T* b, const T* ec, T* xout, T* bc, int l,
-                  int rows, double a, const double* sigma) {
+                  int rows, double a, const double* sigma, const SpaceOp& op) {
   constexpr int H = PRE ? kHaloPre : (WRITE_A ? kHaloPostA : kHaloPost);
   auto kernel = mg_stream_kernel<T, PRE, XIN, DIAG, WRITE_A>;
   // per kernel instantiation (the library drives one device type); a
@@ -731,7 +761,7 @@ hipError_t launch(hipStream_t s, const T* xin, const T* b, const T* ec, T* xout,
     const int64_t waves = groups * ns;
     const unsigned blocks = (unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
     kernel<<<blocks, 64 * kWavesPerBlock, 0, s>>>(xin, b, ec, xout, bc, l, ns, rows, (int)groups,
-                                                  a, sigma);
+                                                  a, sigma, op);
     return hipGetLastError();
   };
   const uint64_t variant = (sizeof(T) == 8 ? 16 : 0) | (PRE ? 8 : 0) | (XIN ? 4 : 0) |
@@ -743,40 +773,55 @@ hipError_t launch(hipStream_t s, const T* xin, const T* b, const T* ec, T* xout,
 
 }  // namespace
 
+// The "/"-diagonal couplings vanish only for the heat equation's K_x (no
+// mass term, no reaction, no mixed diffusion): then the kernels skip them.
+inline bool has_diag(const double* sigma, const SpaceOp& op) {
+  return sigma != nullptr || op.c != 0.0 || op.dxy != 0.0;
+}
+
 template <typename T>
 hipError_t mg_pre_stream(hipStream_t s, const T* xin, const T* b, T* xout, T* bc, int l, int rows,
-                         double a, const double* sigma) {
+                         double a, const double* sigma, const SpaceOp& op) {
+  const bool d = has_diag(sigma, op);
   if (xin) {
-    return sigma ? launch<T, true, true, true, false>(s, xin, b, nullptr, xout, bc, l, rows, a, sigma)
-                 : launch<T, true, true, false, false>(s, xin, b, nullptr, xout, bc, l, rows, a,
-                                                       sigma);
+    return d ? launch<T, true, true, true, false>(s, xin, b, nullptr, xout, bc, l, rows, a, sigma,
+                                                  op)
+             : launch<T, true, true, false, false>(s, xin, b, nullptr, xout, bc, l, rows, a, sigma,
+                                                   op);
   }
-  return sigma ? launch<T, true, false, true, false>(s, xin, b, nullptr, xout, bc, l, rows, a, sigma)
-               : launch<T, true, false, false, false>(s, xin, b, nullptr, xout, bc, l, rows, a,
-                                                      sigma);
+  return d ? launch<T, true, false, true, false>(s, xin, b, nullptr, xout, bc, l, rows, a, sigma,
+                                                 op)
+           : launch<T, true, false, false, false>(s, xin, b, nullptr, xout, bc, l, rows, a, sigma,
+                                                  op);
 }
 
 template <typename T>
 hipError_t mg_post_stream(hipStream_t s, const T* xin, const T* b, const T* ec, T* xout, int l,
-                          int rows, double a, const double* sigma, bool write_Ax) {
+                          int rows, double a, const double* sigma, bool write_Ax,
+                          const SpaceOp& op) {
+  const bool d = has_diag(sigma, op);
   if (write_Ax) {
-    return sigma ? launch<T, false, true, true, true>(s, xin, b, ec, xout, nullptr, l, rows, a, sigma)
-                 : launch<T, false, true, false, true>(s, xin, b, ec, xout, nullptr, l, rows, a,
-                                                       sigma);
+    return d ? launch<T, false, true, true, true>(s, xin, b, ec, xout, nullptr, l, rows, a, sigma,
+                                                  op)
+             : launch<T, false, true, false, true>(s, xin, b, ec, xout, nullptr, l, rows, a, sigma,
+                                                   op);
   }
-  return sigma ? launch<T, false, true, true, false>(s, xin, b, ec, xout, nullptr, l, rows, a, sigma)
-               : launch<T, false, true, false, false>(s, xin, b, ec, xout, nullptr, l, rows, a,
-                                                      sigma);
+  return d ? launch<T, false, true, true, false>(s, xin, b, ec, xout, nullptr, l, rows, a, sigma,
+                                                 op)
+           : launch<T, false, true, false, false>(s, xin, b, ec, xout, nullptr, l, rows, a, sigma,
+                                                  op);
 }
 
 template hipError_t mg_pre_stream<double>(hipStream_t, const double*, const double*, double*,
-                                          double*, int, int, double, const double*);
+                                          double*, int, int, double, const double*,
+                                          const SpaceOp&);
 template hipError_t mg_pre_stream<float>(hipStream_t, const float*, const float*, float*, float*,
-                                         int, int, double, const double*);
+                                         int, int, double, const double*, const SpaceOp&);
 template hipError_t mg_post_stream<double>(hipStream_t, const double*, const double*,
                                            const double*, double*, int, int, double,
-                                           const double*, bool);
+                                           const double*, bool, const SpaceOp&);
 template hipError_t mg_post_stream<float>(hipStream_t, const float*, const float*, const float*,
-                                          float*, int, int, double, const double*, bool);
+                                          float*, int, int, double, const double*, bool,
+                                          const SpaceOp&);
 
 }  // namespace stp

@@ -59,6 +59,7 @@ struct PcgVecs {
 struct stp_ctx {
   int J = 0, K = 0, nrhs = 1, prec = STP_FP64;
   stp_options opt{};
+  stp::SpaceOp op;          // A_x = A_D + c M_x (Section 4); the heat equation by default
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;

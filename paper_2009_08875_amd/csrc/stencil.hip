@@ -5,7 +5,8 @@
 // consecutive time rows.  For each time row it holds the tile plus a one-node
 // halo: the time combinations (A_t X, M_t X, L X, L^T X, built from rows
 // i - 1, i, i + 1 kept in registers) go to LDS, and the spatial stencils
-// (A_x: 5 points, M_x: 7 points on the "/" mesh) read them back.  Every input
+// (A_x: 5 points for the heat equation, 7 with a diffusion tensor or a
+// reaction term; M_x: 7 points on the "/" mesh) read them back.  Every input
 // element is read from HBM once per tile (plus the halo and one time row at
 // each end of a chunk).  Workgroups are numbered so that neighbouring tiles
 // run on the same XCD and share its L2 for the halos.  The chunk length (8 to
@@ -77,12 +78,18 @@ template <typename T>
 __device__ __forceinline__ T Aw(const T (&w)[3][3]) {
   return (((T(4) * w[1][1] - w[1][2]) - w[1][0]) - w[2][1]) - w[0][1];
 }
+// A_x = A_D + c M_x of Section 4 on the window, stencil st = stencil_of(op, 1, 0, K)
+template <typename T>
+__device__ __forceinline__ T Aw_op(const T (&w)[3][3], const T (&st)[4]) {
+  return ((st[0] * w[1][1] + st[1] * (w[1][2] + w[1][0])) + st[2] * (w[2][1] + w[0][1])) +
+         st[3] * (w[2][2] + w[0][0]);
+}
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(kThreads) void row_stencil_kernel(
     const T* __restrict__ in0, const T* __restrict__ in1, const T* __restrict__ extra,
     int64_t extra_stride, T* __restrict__ out0, T* __restrict__ out1, int J, int K, int tiles_x,
-    int tiles, int chunks, int chunk_rows) {
+    int tiles, int chunks, int chunk_rows, SpaceOp op) {
   __shared__ T s0[kHalo], s1[kHalo], s2[kHalo], s3[kHalo];
   const int nb = tiles * chunks;
   const int lb = xcd_remap(blockIdx.x, nb);
@@ -99,6 +106,15 @@ __global__ __launch_bounds__(kThreads) void row_stencil_kernel(
   const T tau6 = T(1.0 / (6.0 * (double)N));
   const double h = 1.0 / (double)(1 << K);
   const T m12 = T(h * h / 12.0);
+  const bool heat = op.heat();
+  T ast[4];
+  {
+    const Stencil a = stencil_of(op, 1.0, 0.0, K);
+    ast[0] = T(a.c0);
+    ast[1] = T(a.cx);
+    ast[2] = T(a.cy);
+    ast[3] = T(a.cd);
+  }
 
   // this thread's halo nodes: offsets into a slab (-1 outside the grid)
   int64_t goff[kPer];
@@ -190,7 +206,7 @@ __global__ __launch_bounds__(kThreads) void row_stencil_kernel(
           w[1][c] = w[2][c];
           w[2][c] = arr[(ly0 + k + 1) * kHX + lx - 1 + c];
         }
-        const T v = is_m ? Mw(w, m12) : Aw(w);
+        const T v = is_m ? Mw(w, m12) : (heat ? Aw(w) : Aw_op(w, ast));
         acc[k] = add ? acc[k] + v : v;
       }
       __builtin_amdgcn_sched_barrier(0);  // keep each pass's window live alone
@@ -232,7 +248,8 @@ __global__ __launch_bounds__(kThreads) void row_stencil_kernel(
 
 template <typename T, int MODE>
 hipError_t launch_rows(hipStream_t s, const T* in0, const T* in1, const T* extra,
-                       int64_t extra_stride, T* out0, T* out1, int J, int K, int nrhs) {
+                       int64_t extra_stride, T* out0, T* out1, int J, int K, int nrhs,
+                       const SpaceOp& op) {
   const int n = grid_n(K);
   const int tiles_x = (n + kTX - 1) / kTX, tiles_y = (n + kTY - 1) / kTY;
   const int tiles = tiles_x * tiles_y;
@@ -240,7 +257,7 @@ hipError_t launch_rows(hipStream_t s, const T* in0, const T* in1, const T* extra
     const int cr = kChunks[c];
     const int chunks = ((1 << J) + 1 + cr - 1) / cr;
     row_stencil_kernel<T, MODE><<<dim3(tiles * chunks, nrhs), kThreads, 0, s>>>(
-        in0, in1, extra, extra_stride, out0, out1, J, K, tiles_x, tiles, chunks, cr);
+        in0, in1, extra, extra_stride, out0, out1, J, K, tiles_x, tiles, chunks, cr, op);
     return hipGetLastError();
   };
   const uint64_t variant = (sizeof(T) == 8 ? 4 : 0) | (uint64_t)MODE;
@@ -252,26 +269,28 @@ hipError_t launch_rows(hipStream_t s, const T* in0, const T* in1, const T* extra
 }  // namespace
 
 template <typename T>
-hipError_t time_stencil_pair(hipStream_t s, const T* X, T* y1, T* y2, int J, int K, int nrhs) {
-  return launch_rows<T, kTimePair>(s, X, nullptr, nullptr, 0, y1, y2, J, K, nrhs);
+hipError_t time_stencil_pair(hipStream_t s, const T* X, T* y1, T* y2, int J, int K, int nrhs,
+                             const SpaceOp& op) {
+  return launch_rows<T, kTimePair>(s, X, nullptr, nullptr, 0, y1, y2, J, K, nrhs, op);
 }
 
 template <typename T>
 hipError_t rhs_stencil_pair(hipStream_t s, const T* g, T* G1, T* G0, int J, int K, int nrhs) {
-  return launch_rows<T, kRhsPair>(s, g, nullptr, nullptr, 0, G1, G0, J, K, nrhs);
+  return launch_rows<T, kRhsPair>(s, g, nullptr, nullptr, 0, G1, G0, J, K, nrhs, SpaceOp{});
 }
 
 template <typename T>
 hipError_t combine(hipStream_t s, const T* z1, const T* z2, const T* extra, int64_t extra_stride,
-                   T* out, int J, int K, int nrhs) {
-  return launch_rows<T, kCombine>(s, z1, z2, extra, extra_stride, out, nullptr, J, K, nrhs);
+                   T* out, int J, int K, int nrhs, const SpaceOp& op) {
+  return launch_rows<T, kCombine>(s, z1, z2, extra, extra_stride, out, nullptr, J, K, nrhs, op);
 }
 
 #define STP_INSTANTIATE_ROWS(T)                                                                   \
-  template hipError_t time_stencil_pair<T>(hipStream_t, const T*, T*, T*, int, int, int);         \
+  template hipError_t time_stencil_pair<T>(hipStream_t, const T*, T*, T*, int, int, int,          \
+                                           const SpaceOp&);                                       \
   template hipError_t rhs_stencil_pair<T>(hipStream_t, const T*, T*, T*, int, int, int);          \
   template hipError_t combine<T>(hipStream_t, const T*, const T*, const T*, int64_t, T*, int, int, \
-                                 int);
+                                 int, const SpaceOp&);
 STP_INSTANTIATE_ROWS(double)
 STP_INSTANTIATE_ROWS(float)
 
