@@ -24,6 +24,9 @@ square with lowest-order elements in space and time:
                       (Theorem 3.1);
   * ``pcg``        -- PCG on S-hat w = f-hat with K_X and the stopping test
                       of Section 3.4, from zero or from an initial guess;
+  * ``space3d``    -- the 3D spatial operators and multigrid on the Kuhn
+                      tetrahedral mesh of the unit cube (Section 5.2's 3D
+                      problem);
   * ``nested``     -- nested iteration over meshes (J - d, K - d) with a
                       tolerance that tracks the discretisation error
                       (Section 4.2).
@@ -42,5 +45,5 @@ direct evaluation of the basis functions, its fixed point by PCG from zero,
 and its error against the exact solution).  The solution values at the benchmark
 sizes are not printed in the paper: the pins above are what fixes them.
 """
-from . import temporal, spatial, multigrid, wavelet, schur, pcg, nested  # noqa: F401
+from . import temporal, spatial, space3d, multigrid, wavelet, schur, pcg, nested  # noqa: F401
 from .pcg import solve  # noqa: F401

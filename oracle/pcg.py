@@ -65,7 +65,7 @@ def solve(J, K, g=None, u0=None, tol=1e-8, maxit=100, **kw):
     ``(u, iterations, history)`` with ``u`` the nodal solution, time-major."""
     P = Problem(J, K, **kw)
     if u0 is None:
-        u0 = np.zeros((P.n, P.n))
+        u0 = np.zeros(P.shape[1:])
     f = P.rhs(g, u0)
     fhat = P.WT(f)
     w, its, hist = pcg(P, fhat, tol, maxit)

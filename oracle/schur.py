@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import multigrid, spatial, temporal, wavelet
+from . import multigrid, space3d, spatial, temporal, wavelet
 
 ALPHA = 0.3  # alpha-scaling of the K_X blocks (Section 5.1)
 
@@ -20,9 +20,15 @@ class Problem:
     (2 V-cycles, 3 smoothing steps, alpha = 0.3)."""
 
     def __init__(self, J: int, K: int, alpha: float = ALPHA, cycles: int = 2, sweeps: int = 3,
-                 D=None, c: float = 0.0):
+                 D=None, c: float = 0.0, dim: int = 2):
         if J < 0 or K < 1:
             raise ValueError("need J >= 0 and K >= 1")
+        if dim not in (2, 3):
+            raise ValueError("dim must be 2 or 3")
+        if dim == 3 and (D is not None or c != 0.0):
+            raise ValueError("the 3D problem is the heat equation (Section 5.2)")
+        # dim 3: Omega = [0, 1]^3 on the Kuhn tetrahedral mesh (space3d)
+        self.dim = dim
         if D is not None and not (D[0] > 0 and D[1] > 0 and D[0] * D[1] > D[2] ** 2):
             raise ValueError("D must be symmetric positive definite")
         if c < 0:
@@ -39,20 +45,26 @@ class Problem:
 
     @property
     def shape(self):
-        return (self.N + 1, self.n, self.n)
+        return (self.N + 1,) + (self.n,) * self.dim
 
     # spatial operators on every row
     def A(self, x):
         """``A_x x``: diffusion (``D``, None = identity) plus reaction ``c M_x``."""
+        if self.dim == 3:
+            return space3d.stiffness(x, self.h)
         if self.D is None and self.c == 0.0:
             return spatial.stiffness(x)
         return spatial.stiffness(x, self.D) + self.c * spatial.mass(x, self.h)
 
     def M(self, x):
+        if self.dim == 3:
+            return space3d.mass(x, self.h)
         return spatial.mass(x, self.h)
 
     def Kx(self, y):
         """``K_x ~ A_x^{-1}`` by multigrid on every row (Section 3.1)."""
+        if self.dim == 3:
+            return space3d.mg_apply(y, self.K, 1.0, 0.0, self.cycles, self.sweeps)
         return multigrid.apply(y, self.K, 1.0, 0.0, self.cycles, self.sweeps, self.D, self.c)
 
     # Lemma 4.2
@@ -93,6 +105,9 @@ class Problem:
         lev = wavelet.row_levels(self.J)
         sigma = 2.0 ** lev.astype(np.float64)
         a = self.alpha
+        if self.dim == 3:
+            Z = space3d.mg_apply(R, self.K, a, sigma, self.cycles, self.sweeps)
+            return space3d.mg_apply(self.A(Z), self.K, a, sigma, self.cycles, self.sweeps)
         Z = multigrid.apply(R, self.K, a, sigma, self.cycles, self.sweeps, self.D, self.c)
         Z = self.A(Z)
         return multigrid.apply(Z, self.K, a, sigma, self.cycles, self.sweeps, self.D, self.c)

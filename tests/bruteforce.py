@@ -214,3 +214,130 @@ def wavelet_basis_matrix(J):
             psi = hat(t, 2 * k + 1, hl) - bl * hat(t, left, hl) - br * hat(t, right, hl)
             W[:, (2 * k + 1) * 2 ** (J - l)] = 2.0 ** (l / 2.0) * psi
     return W
+
+
+# ------------------------------------------------------------ space, 3D (Kuhn mesh)
+
+def kuhn_tets_of_cube():
+    """The 6 tetrahedra of the unit cube around its (1, 1, 1) diagonal: for each
+    ordering of the axes, the path 0 -> e_a -> e_a + e_b -> (1, 1, 1)."""
+    import itertools
+
+    tets = []
+    for p in itertools.permutations(range(3)):
+        v = [(0, 0, 0)]
+        for ax in p:
+            w = list(v[-1])
+            w[ax] += 1
+            v.append(tuple(w))
+        tets.append(v)
+    return tets
+
+
+def p1_assembly_3d(K):
+    """Stiffness and mass of P1 on the Kuhn mesh of the unit cube with 2**K
+    cubes per side, assembled element by element over all tetrahedra; rows
+    are the interior nodes in order ((k - 1) n + (j - 1)) n + (i - 1)."""
+    m = 2 ** K
+    h = 1.0 / m
+    nn = m + 1
+
+    def gid(i, j, k):
+        return (k * nn + j) * nn + i
+
+    A = np.zeros((nn ** 3, nn ** 3))
+    M = np.zeros((nn ** 3, nn ** 3))
+    tets = kuhn_tets_of_cube()
+    for k in range(m):
+        for j in range(m):
+            for i in range(m):
+                for tet in tets:
+                    pts = [(i + a, j + b, k + c) for a, b, c in tet]
+                    P = np.array([[1.0, a * h, b * h, c * h] for a, b, c in pts])
+                    vol = abs(np.linalg.det(P)) / 6.0
+                    G = np.linalg.inv(P)[1:, :]
+                    Kl = vol * G.T @ G
+                    Ml = vol / 20.0 * (np.ones((4, 4)) + np.eye(4))
+                    ids = [gid(*q) for q in pts]
+                    for r in range(4):
+                        for s in range(4):
+                            A[ids[r], ids[s]] += Kl[r, s]
+                            M[ids[r], ids[s]] += Ml[r, s]
+    interior = [gid(i, j, k) for k in range(1, m) for j in range(1, m) for i in range(1, m)]
+    ix = np.ix_(interior, interior)
+    return A[ix], M[ix]
+
+
+def kuhn_eval(values, K, pts):
+    """The P1 function with interior nodal values ``values`` ((n, n, n),
+    zero on the boundary) of the Kuhn mesh with 2**K cubes per side,
+    evaluated at points pts (rows x, y, z in [0, 1]) by locating the cube and
+    its tetrahedron (sort the local coordinates) and using barycentric
+    coordinates."""
+    m = 2 ** K
+    full = np.zeros((m + 1,) * 3)
+    full[1:-1, 1:-1, 1:-1] = values      # [k, j, i]
+    out = np.zeros(len(pts))
+    for t, p in enumerate(pts):
+        q = np.asarray(p) * m
+        c = np.minimum(np.floor(q).astype(int), m - 1)
+        u = q - c
+        order = np.argsort(-u, kind="stable")
+        lam = [1.0 - u[order[0]], u[order[0]] - u[order[1]], u[order[1]] - u[order[2]], u[order[2]]]
+        v = np.zeros(3, dtype=int)
+        val = lam[0] * full[c[2], c[1], c[0]]
+        for r in range(3):
+            v[order[r]] += 1
+            val += lam[r + 1] * full[c[2] + v[2], c[1] + v[1], c[0] + v[0]]
+        out[t] = val
+    return out
+
+
+def dense_mg_3d(b, K, a, sigma, cycles=2, sweeps=3):
+    """Two V-cycles written with dense matrices: Gauss-Seidel node by node in the
+    colours (i + j + k) mod 4 (forward 0..3 before, backward 3..0 after the
+    coarse grid), P by evaluating coarse functions at the fine nodes."""
+    ops = {k: p1_assembly_3d(k) for k in range(1, K + 1)}
+
+    def colours(k):
+        n = 2 ** k - 1
+        return np.array([(i + 1 + j + 1 + l + 1) % 4 for l in range(n) for j in range(n)
+                         for i in range(n)])
+
+    def prol(k):
+        nf, nc = 2 ** k - 1, 2 ** (k - 1) - 1
+        pts = [((i + 1) / 2 ** k, (j + 1) / 2 ** k, (l + 1) / 2 ** k)
+               for l in range(nf) for j in range(nf) for i in range(nf)]
+        P = np.zeros((nf ** 3, nc ** 3))
+        for col in range(nc ** 3):
+            e = np.zeros(nc ** 3)
+            e[col] = 1.0
+            P[:, col] = kuhn_eval(e.reshape(nc, nc, nc), k - 1, pts)
+        return P
+
+    Ps = {k: prol(k) for k in range(2, K + 1)}
+
+    def cycle(b, x, k):
+        A, M = ops[k]
+        C = a * A + sigma * M
+        if k == 1:
+            return b / C[0, 0]
+        col = colours(k)
+        x = x.copy()
+        for _ in range(sweeps):
+            for c in range(4):
+                for p in np.nonzero(col == c)[0]:
+                    x[p] = (b[p] - (C[p] @ x - C[p, p] * x[p])) / C[p, p]
+        P = Ps[k]
+        ec = cycle(P.T @ (b - C @ x), np.zeros(P.shape[1]), k - 1)
+        x = x + P @ ec
+        for _ in range(sweeps):
+            for c in (3, 2, 1, 0):
+                for p in np.nonzero(col == c)[0]:
+                    x[p] = (b[p] - (C[p] @ x - C[p, p] * x[p])) / C[p, p]
+        return x
+
+    x = np.zeros_like(b)
+    for _ in range(cycles):
+        x = cycle(b, x, K)
+    return x

@@ -642,3 +642,115 @@ def test_reaction_diffusion_converges_to_exact_solution():
         exact = np.exp(-rate * t)[:, None, None] * s[None]
         errs.append(np.abs(u - exact).max())
     assert errs[0] / errs[1] >= 1.8 and errs[1] / errs[2] >= 1.8, errs
+
+
+# -------------------------------------------- 3D problem (Section 5.2, Kuhn mesh)
+
+def _cube_sin(K):
+    n = 2 ** K - 1
+    x = np.arange(1, n + 1) / 2 ** K
+    s = np.sin(np.pi * x)
+    return np.einsum("i,j,k->kji", s, s, s)
+
+
+@pytest.mark.parametrize("K", [1, 2])
+def test_3d_matrices_match_assembly(K):
+    from oracle import space3d
+
+    A, M = bf.p1_assembly_3d(K)
+    n, h = 2 ** K - 1, 2.0 ** -K
+    assert np.allclose(op_matrix(lambda x: space3d.stiffness(x, h), (n, n, n)), A, atol=1e-14)
+    assert np.allclose(op_matrix(lambda x: space3d.mass(x, h), (n, n, n)), M, atol=1e-16)
+
+
+def test_3d_stiffness_spectrum_and_mass_rows():
+    """A_x on the Kuhn mesh is h times the 7-point Laplacian: eigenvalues
+    h sum_d (2 - 2 cos(p_d pi h)); interior rows of M sum to h^3."""
+    from oracle import space3d
+
+    K = 3
+    n, h = 2 ** K - 1, 2.0 ** -K
+    Am = op_matrix(lambda x: space3d.stiffness(x, h), (n, n, n))
+    c = 2 - 2 * np.cos(np.arange(1, n + 1) * np.pi * h)
+    lam = np.sort((h * (c[:, None, None] + c[None, :, None] + c[None, None, :])).ravel())
+    assert np.allclose(np.linalg.eigvalsh(Am), lam, atol=1e-12)
+    rows = space3d.mass(np.ones((n, n, n)), h)
+    assert abs(rows[n // 2, n // 2, n // 2] - h ** 3) <= 1e-16
+
+
+def test_3d_prolongation_is_interpolation():
+    """P carries a coarse P1 function to the fine mesh by its values at the
+    fine nodes (located tetrahedron, barycentric coordinates); the
+    restriction is its transpose."""
+    from oracle import space3d
+
+    K = 3
+    e = np.random.default_rng(3).standard_normal((3, 3, 3))
+    nf = 2 ** K - 1
+    pts = [((i + 1) / 2 ** K, (j + 1) / 2 ** K, (k + 1) / 2 ** K)
+           for k in range(nf) for j in range(nf) for i in range(nf)]
+    ref = bf.kuhn_eval(e, K - 1, pts)
+    assert np.allclose(space3d.prolong(e).ravel(), ref, atol=1e-14)
+    P = op_matrix(space3d.prolong, (3, 3, 3))
+    R = op_matrix(space3d.restrict, (7, 7, 7))
+    assert np.array_equal(P.T, R)
+
+
+@pytest.mark.parametrize("K,a,sigma", [(2, 1.0, 0.0), (3, 1.0, 0.0), (3, 0.3, 16.0)])
+def test_3d_multigrid_matches_dense_vcycle(K, a, sigma):
+    from oracle import space3d
+
+    n = 2 ** K - 1
+    b = np.random.default_rng(K).standard_normal((n, n, n))
+    got = space3d.mg_apply(b, K, a, sigma)
+    ref = bf.dense_mg_3d(b.ravel(), K, a, sigma)
+    assert np.allclose(got.ravel(), ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+def test_3d_multigrid_symmetric_positive_definite():
+    from oracle import space3d
+
+    K = 2
+    Kd = op_matrix(lambda b: space3d.mg_apply(b, K, 0.3, 4.0), (3, 3, 3))
+    assert np.abs(Kd - Kd.T).max() <= 1e-13 * np.abs(Kd).max()
+    assert np.linalg.eigvalsh(0.5 * (Kd + Kd.T)).min() > 0
+
+
+def test_3d_S_lemma41_equals_lemma42():
+    J, K = 1, 2
+    P = Problem(J, K, dim=3)
+    N = 2 ** J
+    O, T, Nm = bf.legendre_test_space(N)
+    A, M = bf.p1_assembly_3d(K)
+    Kx = op_matrix(P.Kx, (P.n,) * 3)
+    B = np.kron(T, M) + np.kron(Nm, A)
+    G = np.zeros((N + 1, N + 1))
+    G[0, 0] = 1.0
+    S41 = B.T @ np.kron(np.diag(1.0 / O), Kx) @ B + np.kron(G, M)
+    S42 = op_matrix(P.S, P.shape)
+    assert np.abs(S42 - S41).max() <= 1e-12 * np.abs(S41).max()
+
+
+def test_3d_pcg_matches_dense_solve():
+    J, K = 2, 2
+    P = Problem(J, K, dim=3)
+    rng = np.random.default_rng(23)
+    g = rng.standard_normal(P.shape)
+    u0 = rng.standard_normal(P.shape[1:])
+    S = op_matrix(P.S, P.shape)
+    exact = np.linalg.solve(S, P.rhs(g, u0).ravel())
+    u, its, _ = oracle.solve(J, K, g, u0, tol=1e-13, maxit=200, dim=3)
+    assert np.linalg.norm(u.ravel() - exact) <= 1e-11 * np.linalg.norm(exact)
+
+
+@pytest.mark.slow
+def test_3d_converges_to_exact_solution():
+    """Section 5.2's 3D solution exp(-3 pi^2 t) sin(pi x) sin(pi y) sin(pi z):
+    the nodal error falls by more than 1.8 per joint refinement of h and tau."""
+    errs = []
+    for L in (2, 3, 4):
+        s = _cube_sin(L)
+        u, _, _ = oracle.solve(L, L, None, s, tol=1e-12, maxit=200, dim=3)
+        t = np.arange(2 ** L + 1) / 2 ** L
+        errs.append(np.abs(u - np.exp(-3 * np.pi ** 2 * t)[:, None, None, None] * s[None]).max())
+    assert errs[0] / errs[1] >= 1.8 and errs[1] / errs[2] >= 1.8, errs
