@@ -85,6 +85,13 @@ typedef struct {
                            D = [[d0, d2], [d2, d1]], constant, symmetric positive
                            definite (all three 0 -> identity, the heat equation) */
   double reaction;      /* c >= 0 (0: no reaction term) */
+  int dim;              /* space dimensions: 0 or 2 -> the unit square; 3 -> the unit
+                           cube of Section 5.2's 3D problem on the Kuhn tetrahedral mesh
+                           (each cube cut into 6 tetrahedra around its (1,1,1) diagonal),
+                           1 <= K <= 8, N_x = (2^K - 1)^3, node (a, b, c) at offset
+                           ((c - 1)(2^K - 1) + (b - 1))(2^K - 1) + (a - 1); the heat
+                           equation only (no nesting, diffusion or reaction), not for
+                           the server; stp_footprint counts two dimensions */
 } stp_options;
 
 typedef struct {

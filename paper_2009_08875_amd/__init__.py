@@ -36,7 +36,8 @@ class stp_options(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("vcycles", ctypes.c_int), ("sweeps", ctypes.c_int),
                 ("maxit", ctypes.c_int), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
                 ("graph", ctypes.c_int), ("nested", ctypes.c_int),
-                ("diffusion", ctypes.c_double * 3), ("reaction", ctypes.c_double)]
+                ("diffusion", ctypes.c_double * 3), ("reaction", ctypes.c_double),
+                ("dim", ctypes.c_int)]
 
 
 class stp_stats(ctypes.Structure):

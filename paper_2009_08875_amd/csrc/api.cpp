@@ -92,6 +92,19 @@ struct Arena {
 };
 
 template <typename T>
+stp_status plan_mg3(Arena& ar, MgScratch<T>& mg, Mg3Work<T>& w, int K, int64_t chunk_rows) {
+  mg.K = K;
+  mg.chunk_rows = chunk_rows;
+  STP_TRY(ar.get(&w.x[K], chunk_rows * slab3_elems(K)));
+  for (int l = 2; l <= K; ++l) STP_TRY(ar.get(&w.r[l], chunk_rows * slab3_elems(l)));
+  for (int l = 1; l < K; ++l) {
+    STP_TRY(ar.get(&w.x[l], chunk_rows * slab3_elems(l)));
+    STP_TRY(ar.get(&w.b[l], chunk_rows * slab3_elems(l)));
+  }
+  return STP_OK;
+}
+
+template <typename T>
 stp_status plan_mg(Arena& ar, MgScratch<T>& mg, int K, int64_t chunk_rows) {
   mg.K = K;
   mg.chunk_rows = chunk_rows;
@@ -105,12 +118,15 @@ stp_status plan_mg(Arena& ar, MgScratch<T>& mg, int K, int64_t chunk_rows) {
 }
 
 template <typename T>
-stp_status plan_ops(Arena& ar, Ops<T>& o, int K, int64_t rows, int64_t vec) {
+stp_status plan_ops(Arena& ar, Ops<T>& o, int K, int64_t rows, int64_t vec, int dim) {
   STP_TRY(ar.get(&o.X, vec));
   STP_TRY(ar.get(&o.y, 2 * vec));
   STP_TRY(ar.get(&o.z, 2 * vec));
   // S and f apply K_x to two arrays at once (2 * rows rows in one launch)
-  STP_TRY(plan_mg(ar, o.mg, K, std::min<int64_t>(2 * rows, kMaxGridY)));
+  if (dim == 3)
+    STP_TRY(plan_mg3(ar, o.mg, o.mg3, K, std::min<int64_t>(2 * rows, kMaxGridY)));
+  else
+    STP_TRY(plan_mg(ar, o.mg, K, std::min<int64_t>(2 * rows, kMaxGridY)));
   o.ready = !ar.dry;
   return STP_OK;
 }
@@ -135,7 +151,7 @@ stp_status plan_context(Arena& ar, stp_ctx* c) {
   STP_TRY(ar.get(&c->u, vec));
   STP_TRY(ar.get(&c->sigma, c->rows));
   STP_TRY(ar.get(&c->rhoref, c->nrhs));
-  STP_TRY(ar.get(&c->partials, (int64_t)c->nrhs * std::max(1024, analysis_dot_blocks(c->K))));
+  STP_TRY(ar.get(&c->partials, (int64_t)c->nrhs * std::max(1024, analysis_dot_blocks(c->slab))));
   STP_TRY(ar.get(&c->tolv, c->nrhs));
   STP_TRY(ar.get(&c->sc.rho, c->nrhs));
   STP_TRY(ar.get(&c->sc.rho0, c->nrhs));
@@ -147,7 +163,7 @@ stp_status plan_context(Arena& ar, stp_ctx* c) {
   STP_TRY(ar.get(&c->sc.active, c->nrhs));
   STP_TRY(ar.get(&c->sc.its, c->nrhs));
   STP_TRY(ar.get(&c->sc.status, c->nrhs));
-  STP_TRY(plan_ops(ar, c->ops64, c->K, c->rows, vec));
+  STP_TRY(plan_ops(ar, c->ops64, c->K, c->rows, vec, c->dim));
   if (c->prec == STP_FP64) {
     STP_TRY(plan_pcg(ar, c->pcg64, vec, false));
   } else {
@@ -159,7 +175,7 @@ stp_status plan_context(Arena& ar, stp_ctx* c) {
     STP_TRY(ar.get(&c->ms.inner_its, c->nrhs));
     STP_TRY(ar.get(&c->w64, vec));
     STP_TRY(ar.get(&c->r64, vec));
-    STP_TRY(plan_ops(ar, c->ops32, c->K, c->rows, vec));
+    STP_TRY(plan_ops(ar, c->ops32, c->K, c->rows, vec, c->dim));
     STP_TRY(plan_pcg(ar, c->pcg32, vec, true));
   }
   return STP_OK;
@@ -196,6 +212,18 @@ template <>
 Ops<double>& ops_of<double>(stp_ctx* c) { return c->ops64; }
 template <>
 Ops<float>& ops_of<float>(stp_ctx* c) { return c->ops32; }
+
+// Compact FP64 rows of nx values <-> slabs, in the context's dimension.
+template <typename T>
+hipError_t pack_rows(const stp_ctx* c, const double* src, T* dst, int rows) {
+  return c->dim == 3 ? pack3<T>(c->stream, src, dst, c->K, rows)
+                     : pack<T>(c->stream, src, dst, c->K, rows);
+}
+template <typename T>
+hipError_t unpack_rows(const stp_ctx* c, const T* src, double* dst, int rows) {
+  return c->dim == 3 ? unpack3<T>(c->stream, src, dst, c->K, rows)
+                     : unpack<T>(c->stream, src, dst, c->K, rows);
+}
 
 // ------------------------------------------------------------ kernel timing
 
@@ -251,6 +279,16 @@ template <typename T>
 stp_status mg_apply(stp_ctx* c, MgScratch<T>& mg, const T* b, T* x, int64_t rows, double a,
                     const double* sigma, bool write_Ax = false) {
   const int K = c->K;
+  if (c->dim == 3) {
+    // three dimensions (space3d.hip): the chunk's rows through mg3_apply
+    const Ops<T>& o = ops_of<T>(c);
+    for (int64_t r0 = 0; r0 < rows; r0 += mg.chunk_rows) {
+      const int nr = (int)std::min<int64_t>(mg.chunk_rows, rows - r0);
+      HIP_TRY(mg3_apply<T>(c->stream, o.mg3, b + r0 * c->slab, x + r0 * c->slab, K, nr, a,
+                           sigma ? sigma + r0 : nullptr, c->opt.vcycles, write_Ax));
+    }
+    return STP_OK;
+  }
   const int64_t slab = slab_elems(K);
   for (int64_t r0 = 0; r0 < rows; r0 += mg.chunk_rows) {
     const int nr = (int)std::min<int64_t>(mg.chunk_rows, rows - r0);
@@ -301,8 +339,7 @@ stp_status mg_apply(stp_ctx* c, MgScratch<T>& mg, const T* b, T* x, int64_t rows
 // interior node of `rows` time rows.
 template <typename T>
 double row_bytes(const stp_ctx* c, int64_t rows, double words) {
-  const double n = (double)grid_n(c->K);
-  return words * sizeof(T) * (double)rows * n * n;
+  return words * sizeof(T) * (double)rows * (double)c->nx;
 }
 
 // out = S X (Lemma 4.2) for `nrhs` right-hand sides starting at X.
@@ -316,12 +353,14 @@ stp_status S_apply(stp_ctx* c, Ops<T>& o, const T* X, T* out, int nrhs) {
   T* z2 = o.z + v;
   // X in; y1, y2 out
   STP_TRY(timed_launch(c, STP_KERNEL_TIME_STENCIL, row_bytes<T>(c, rows, 3.0), [&] {
+    if (c->dim == 3) return time_stencil_pair3<T>(c->stream, X, y1, y2, c->J, c->K, nrhs);
     return time_stencil_pair<T>(c->stream, X, y1, y2, c->J, c->K, nrhs, c->op);
   }));
   // y1 | y2 and z1 | z2 are contiguous: one K_x application over both
   STP_TRY(mg_apply<T>(c, o.mg, y1, z1, 2 * rows, 1.0, nullptr));
   // z1, z2 in; S X out (row 0's M X_0 term is one row in 2^J + 1)
   STP_TRY(timed_launch(c, STP_KERNEL_COMBINE, row_bytes<T>(c, rows, 3.0), [&] {
+    if (c->dim == 3) return combine3<T>(c->stream, z1, z2, X, c->per_rhs, out, c->J, c->K, nrhs);
     return combine<T>(c->stream, z1, z2, X, c->per_rhs, out, c->J, c->K, nrhs, c->op);
   }));
   return STP_OK;
@@ -330,9 +369,9 @@ stp_status S_apply(stp_ctx* c, Ops<T>& o, const T* X, T* out, int nrhs) {
 // out = S-hat p = W^T S W p (eq. (11)).
 template <typename T>
 stp_status Shat_apply(stp_ctx* c, Ops<T>& o, const T* p, T* out, int nrhs) {
-  HIP_TRY(synthesis<T>(c->stream, p, o.X, c->J, c->K, nrhs));
+  HIP_TRY(synthesis<T>(c->stream, p, o.X, c->J, c->slab, nrhs));
   STP_TRY(S_apply<T>(c, o, o.X, out, nrhs));
-  HIP_TRY(wavelet<T>(c->stream, out, c->J, c->K, nrhs, false));
+  HIP_TRY(wavelet<T>(c->stream, out, c->J, c->slab, nrhs, false));
   return STP_OK;
 }
 
@@ -343,12 +382,12 @@ template <typename T>
 stp_status Shat_iteration(stp_ctx* c, Ops<T>& o, PcgVecs<T>& v) {
   // z, p in; p, X out
   STP_TRY(timed_launch(c, STP_KERNEL_SYN_UPDATE, row_bytes<T>(c, c->rows, 4.0), [&] {
-    return synthesis_update<T>(c->stream, v.p, v.z, c->sc.beta, o.X, c->J, c->K, c->nrhs);
+    return synthesis_update<T>(c->stream, v.p, v.z, c->sc.beta, o.X, c->J, c->slab, c->nrhs);
   }));
   STP_TRY(S_apply<T>(c, o, o.X, v.q, c->nrhs));
   // q, p in; q out
   STP_TRY(timed_launch(c, STP_KERNEL_ANA_DOT, row_bytes<T>(c, c->rows, 3.0), [&] {
-    return analysis_dot<T>(c->stream, v.q, v.p, c->partials, c->sc.pq, c->J, c->K, c->nrhs);
+    return analysis_dot<T>(c->stream, v.q, v.p, c->partials, c->sc.pq, c->J, c->slab, c->nrhs);
   }));
   return STP_OK;
 }
@@ -375,12 +414,18 @@ stp_status rhs_apply(stp_ctx* c, double* f) {
   if (any_g) {
     double* G1 = o.y;
     double* G0 = o.y + v;
-    HIP_TRY(rhs_stencil_pair<double>(c->stream, c->g, G1, G0, c->J, c->K, c->nrhs));
+    if (c->dim == 3)
+      HIP_TRY(rhs_stencil_pair3<double>(c->stream, c->g, G1, G0, c->J, c->K, c->nrhs));
+    else
+      HIP_TRY(rhs_stencil_pair<double>(c->stream, c->g, G1, G0, c->J, c->K, c->nrhs));
     STP_TRY(mg_apply<double>(c, o.mg, G1, z1, 2 * c->rows, 1.0, nullptr));  // G1 | G0 -> z1 | z2
   } else {
     HIP_TRY(hipMemsetAsync(z1, 0, sizeof(double) * 2 * v, c->stream));
   }
-  HIP_TRY(combine<double>(c->stream, z1, z2, c->u0, c->slab, f, c->J, c->K, c->nrhs, c->op));
+  if (c->dim == 3)
+    HIP_TRY(combine3<double>(c->stream, z1, z2, c->u0, c->slab, f, c->J, c->K, c->nrhs));
+  else
+    HIP_TRY(combine<double>(c->stream, z1, z2, c->u0, c->slab, f, c->J, c->K, c->nrhs, c->op));
   return STP_OK;
 }
 
@@ -511,13 +556,13 @@ stp_status finish_unit(stp_ctx* c) {
   double* hs = c->h_stats;
   int* hi = (int*)(c->h_stats + 2 * nr);
   if (c->prec == STP_FP64) {
-    HIP_TRY(synthesis<double>(c->stream, c->pcg64.w, c->u, c->J, c->K, nr));
+    HIP_TRY(synthesis<double>(c->stream, c->pcg64.w, c->u, c->J, c->slab, nr));
     HIP_TRY(hipMemcpyAsync(hs, c->sc.rho, sizeof(double) * nr, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(hs + nr, c->sc.rho0, sizeof(double) * nr, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(hi, c->sc.its, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(hi + nr, c->sc.status, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
   } else {
-    HIP_TRY(synthesis<double>(c->stream, c->w64, c->u, c->J, c->K, nr));
+    HIP_TRY(synthesis<double>(c->stream, c->w64, c->u, c->J, c->slab, nr));
     HIP_TRY(hipMemcpyAsync(hs, c->ms.rel, sizeof(double) * nr, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(hi, c->ms.inner_its, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(hi + nr, c->ms.status, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
@@ -595,7 +640,7 @@ stp_status drive_begin(stp_ctx* c, const double* tol, const stp_ctx* coarse) {
   HIP_TRY(hipEventRecord(c->ev0, c->stream));
   HIP_TRY(hipMemcpyAsync(c->tolv, c->h_tol, sizeof(double) * nr, hipMemcpyHostToDevice, c->stream));
   STP_TRY(rhs_apply(c, c->fhat));
-  HIP_TRY(wavelet<double>(c->stream, c->fhat, c->J, c->K, nr, false));
+  HIP_TRY(wavelet<double>(c->stream, c->fhat, c->J, c->slab, nr, false));
   if (c->prec == STP_FP64) {
     if (coarse)
       STP_TRY(pcg_init_from(c, coarse, c->tolv));
@@ -679,7 +724,7 @@ stp_status ensure_ops(stp_ctx* c, Ops<T>& o) {
   ar.dry = false;
   ar.list = &c->allocations;
   ar.stream = c->stream;
-  STP_TRY(plan_ops(ar, o, c->K, c->rows, c->vec));
+  STP_TRY(plan_ops(ar, o, c->K, c->rows, c->vec, c->dim));
   c->bytes += ar.bytes;
   return STP_OK;
 }
@@ -710,12 +755,15 @@ stp_status check_sizes(int J, int K, int nrhs, int precision) {
   return STP_OK;
 }
 
-void init_dims(stp_ctx* c, int J, int K, int nrhs, int precision) {
+void init_dims(stp_ctx* c, int J, int K, int nrhs, int precision, int dim = 2) {
   c->J = J;
   c->K = K;
   c->nrhs = nrhs;
   c->prec = precision;
-  c->slab = slab_elems(K);
+  c->dim = dim;
+  const int64_t n = grid_n(K);
+  c->nx = dim == 3 ? n * n * n : n * n;
+  c->slab = dim == 3 ? slab3_elems(K) : slab_elems(K);
   c->rows_per = (1 << J) + 1;
   c->rows = (int64_t)nrhs * c->rows_per;
   c->per_rhs = c->rows_per * c->slab;
@@ -786,6 +834,16 @@ stp_status stp_create(int J, int K, int nrhs, int precision, const stp_options* 
     set_error("the diffusion tensor must be symmetric positive definite and the reaction >= 0");
     return STP_E_INVALID_ARG;
   }
+  const int dim = o.dim == 3 ? 3 : 2;
+  if (o.dim != 0 && o.dim != 2 && o.dim != 3) {
+    set_error("dim must be 0, 2 or 3");
+    return STP_E_INVALID_ARG;
+  }
+  if (dim == 3 && (K > kMaxK3 || o.nested > 0 || o.diffusion[2] != 0.0 ||
+                   o.diffusion[0] != 1.0 || o.diffusion[1] != 1.0 || o.reaction != 0.0)) {
+    set_error("the 3D problem is the heat equation with K <= 8, without nested iteration");
+    return dim == 3 && K > kMaxK3 ? STP_E_INVALID_ARG : STP_E_UNSUPPORTED;
+  }
   if (o.nested > 0 && precision != STP_FP64) {
     set_error("nested iteration is implemented for STP_FP64");
     return STP_E_UNSUPPORTED;
@@ -796,7 +854,7 @@ stp_status stp_create(int J, int K, int nrhs, int precision, const stp_options* 
     set_error("host allocation failed");
     return STP_E_OUT_OF_MEMORY;
   }
-  init_dims(c, J, K, nrhs, precision);
+  init_dims(c, J, K, nrhs, precision, dim);
   c->opt = o;
   c->op.dxx = o.diffusion[0];
   c->op.dyy = o.diffusion[1];
@@ -829,7 +887,7 @@ stp_status stp_create(int J, int K, int nrhs, int precision, const stp_options* 
     // refuse early when the context cannot fit in what the device has free
     Arena dry;
     stp_ctx probe;
-    init_dims(&probe, J, K, nrhs, precision);
+    init_dims(&probe, J, K, nrhs, precision, dim);
     size_t free_b = 0, total_b = 0;
     bool ok = plan_context(dry, &probe) == STP_OK;
     for (int d = 1; ok && d <= depth; ++d) {
@@ -890,10 +948,9 @@ stp_status stp_set_u0(stp_ctx* c, int rhs, const double* u0, int on_device) {
     HIP_TRY(hipMemsetAsync(dst, 0, sizeof(double) * c->slab, c->stream));
     return STP_OK;
   }
-  const int64_t nn = (int64_t)grid_n(c->K) * grid_n(c->K);
   double* tmp = c->ops64.z;  // compact staging area (large enough: >= vec elements)
-  STP_TRY(stage_in(c, u0, on_device, nn, tmp));
-  HIP_TRY(pack<double>(c->stream, tmp, dst, c->K, 1));
+  STP_TRY(stage_in(c, u0, on_device, c->nx, tmp));
+  HIP_TRY(pack_rows<double>(c, tmp, dst, 1));
   return STP_OK;
 }
 
@@ -905,10 +962,9 @@ stp_status stp_set_g(stp_ctx* c, int rhs, const double* g, int on_device) {
     c->has_g[rhs] = 0;
     return STP_OK;
   }
-  const int64_t nn = (int64_t)grid_n(c->K) * grid_n(c->K);
   double* tmp = c->ops64.z;
-  STP_TRY(stage_in(c, g, on_device, nn * c->rows_per, tmp));
-  HIP_TRY(pack<double>(c->stream, tmp, dst, c->K, (int)c->rows_per));
+  STP_TRY(stage_in(c, g, on_device, c->nx * c->rows_per, tmp));
+  HIP_TRY(pack_rows<double>(c, tmp, dst, (int)c->rows_per));
   c->has_g[rhs] = 1;
   return STP_OK;
 }
@@ -986,14 +1042,13 @@ stp_status stp_get_solution(stp_ctx* c, int rhs, double* u, int on_device) {
     set_error("no solve has run on this context");
     return STP_E_INVALID_ARG;
   }
-  const int64_t nn = (int64_t)grid_n(c->K) * grid_n(c->K);
-  const int64_t count = nn * c->rows_per;
+  const int64_t count = c->nx * c->rows_per;
   double* src = c->u + (int64_t)rhs * c->per_rhs;
   if (on_device) {
-    HIP_TRY(unpack<double>(c->stream, src, u, c->K, (int)c->rows_per));
+    HIP_TRY(unpack_rows<double>(c, src, u, (int)c->rows_per));
   } else {
     double* tmp = c->ops64.z;
-    HIP_TRY(unpack<double>(c->stream, src, tmp, c->K, (int)c->rows_per));
+    HIP_TRY(unpack_rows<double>(c, src, tmp, (int)c->rows_per));
     HIP_TRY(hipMemcpyAsync(u, tmp, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
   }
@@ -1042,15 +1097,15 @@ stp_status apply_op_t(stp_ctx* c, int op, const double* in_dev, double* out_dev)
   const int rows = (int)c->rows_per;
   T* in_t = (T*)(c->apply_buf + 2 * c->per_rhs);
   T* out_t = (T*)(c->apply_buf + 3 * c->per_rhs);
-  HIP_TRY(pack<T>(c->stream, in_dev, in_t, K, rows));
+  HIP_TRY(pack_rows<T>(c, in_dev, in_t, rows));
   switch (op) {
     case STP_OP_W:
       HIP_TRY(copy<T>(c->stream, in_t, out_t, c->per_rhs));
-      HIP_TRY(wavelet<T>(c->stream, out_t, J, K, 1, true));
+      HIP_TRY(wavelet<T>(c->stream, out_t, J, c->slab, 1, true));
       break;
     case STP_OP_WT:
       HIP_TRY(copy<T>(c->stream, in_t, out_t, c->per_rhs));
-      HIP_TRY(wavelet<T>(c->stream, out_t, J, K, 1, false));
+      HIP_TRY(wavelet<T>(c->stream, out_t, J, c->slab, 1, false));
       break;
     case STP_OP_S:
       STP_TRY(S_apply<T>(c, o, in_t, out_t, 1));
@@ -1065,16 +1120,22 @@ stp_status apply_op_t(stp_ctx* c, int op, const double* in_dev, double* out_dev)
       STP_TRY(mg_apply<T>(c, o.mg, in_t, out_t, rows, 1.0, nullptr));
       break;
     case STP_OP_A:
-      HIP_TRY(apply_A<T>(c->stream, in_t, out_t, K, rows, c->op));
+      if (c->dim == 3)
+        HIP_TRY(apply_A3<T>(c->stream, in_t, out_t, K, rows));
+      else
+        HIP_TRY(apply_A<T>(c->stream, in_t, out_t, K, rows, c->op));
       break;
     case STP_OP_M:
-      HIP_TRY(apply_M<T>(c->stream, in_t, out_t, K, rows));
+      if (c->dim == 3)
+        HIP_TRY(apply_M3<T>(c->stream, in_t, out_t, K, rows));
+      else
+        HIP_TRY(apply_M<T>(c->stream, in_t, out_t, K, rows));
       break;
     default:
       set_error("unknown operator");
       return STP_E_INVALID_ARG;
   }
-  HIP_TRY(unpack<T>(c->stream, out_t, out_dev, K, rows));
+  HIP_TRY(unpack_rows<T>(c, out_t, out_dev, rows));
   return STP_OK;
 }
 
@@ -1095,8 +1156,7 @@ extern "C" stp_status stp_apply(stp_ctx* c, int op, int precision, int rhs, cons
     set_error("unknown operator");
     return STP_E_INVALID_ARG;
   }
-  const int64_t nn = (int64_t)grid_n(c->K) * grid_n(c->K);
-  const int64_t count = nn * c->rows_per;
+  const int64_t count = c->nx * c->rows_per;
   if (!c->apply_buf) {
     Arena ar;
     ar.dry = false;
@@ -1110,7 +1170,7 @@ extern "C" stp_status stp_apply(stp_ctx* c, int op, int precision, int rhs, cons
   if (op == STP_OP_RHS) {
     double* f = (double*)(c->apply_buf + 3 * c->per_rhs);
     STP_TRY(rhs_apply(c, f));
-    HIP_TRY(unpack<double>(c->stream, f, out_dev, c->K, (int)c->rows_per));
+    HIP_TRY(unpack_rows<double>(c, f, out_dev, (int)c->rows_per));
   } else {
     if (!on_device)
       HIP_TRY(hipMemcpyAsync(in_dev, in, sizeof(double) * count, hipMemcpyHostToDevice, c->stream));

@@ -94,23 +94,25 @@ hipError_t apply_A(hipStream_t s, const T* x, T* y, int K, int rows, const Space
 template <typename T>
 hipError_t apply_M(hipStream_t s, const T* x, T* y, int K, int rows);
 
-// ---- three-point wavelet transform along time, in place (Section 3.3).
+// ---- three-point wavelet transform along time, in place (Section 3.3).  It
+// acts on every element of a time row alike, so it takes the row length
+// (slab: slab_elems(K) in 2D, slab3_elems(K) in 3D).
 template <typename T>
-hipError_t wavelet(hipStream_t s, T* X, int J, int K, int nrhs, bool synthesis);
+hipError_t wavelet(hipStream_t s, T* X, int J, int64_t slab, int nrhs, bool synthesis);
 // dst = W src (src == dst allowed; for J = 0 a copy).
 template <typename T>
-hipError_t synthesis(hipStream_t s, const T* src, T* dst, int J, int K, int nrhs);
+hipError_t synthesis(hipStream_t s, const T* src, T* dst, int J, int64_t slab, int nrhs);
 // X = W p after the conjugate-gradient update p = z + beta_b p (p is updated
 // in place; X must not alias p, z).
 template <typename T>
 hipError_t synthesis_update(hipStream_t s, T* p, const T* z, const double* beta, T* X, int J,
-                            int K, int nrhs);
+                            int64_t slab, int nrhs);
 // X = W^T X in place, and out_b = p_b^T X_b (FP64, deterministic); partials
-// holds nrhs * analysis_dot_blocks(K) values.
-int analysis_dot_blocks(int K);
+// holds nrhs * analysis_dot_blocks(slab) values.
+int analysis_dot_blocks(int64_t slab);
 template <typename T>
 hipError_t analysis_dot(hipStream_t s, T* X, const T* p, double* partials, double* out, int J,
-                        int K, int nrhs);
+                        int64_t slab, int nrhs);
 
 // ---- vector operations over `nrhs` segments of `n` elements (segment b at
 // offset b * n).  Dots are deterministic: a fixed block decomposition of each
@@ -190,6 +192,38 @@ hipError_t add_correction(hipStream_t s, double* w, const float* d, int64_t n, i
                           const int* status);
 // sigma[b * (N+1) + i] = 2^row_level(i, J)
 hipError_t fill_level_sigma(hipStream_t s, double* sigma, int J, int nrhs);
+
+// ---- three space dimensions (Section 5.2's 3D problem, space3d.hip): slabs
+// of slab3_elems(l) elements, the Kuhn tetrahedral mesh of the unit cube.
+// Same contracts as the two-dimensional launchers above.
+template <typename T>
+hipError_t pack3(hipStream_t s, const double* src, T* dst, int K, int rows);
+template <typename T>
+hipError_t unpack3(hipStream_t s, const T* src, double* dst, int K, int rows);
+template <typename T>
+hipError_t apply_A3(hipStream_t s, const T* x, T* y, int K, int rows);
+template <typename T>
+hipError_t apply_M3(hipStream_t s, const T* x, T* y, int K, int rows);
+template <typename T>
+hipError_t time_stencil_pair3(hipStream_t s, const T* X, T* y1, T* y2, int J, int K, int nrhs);
+template <typename T>
+hipError_t rhs_stencil_pair3(hipStream_t s, const T* g, T* G1, T* G0, int J, int K, int nrhs);
+template <typename T>
+hipError_t combine3(hipStream_t s, const T* z1, const T* z2, const T* extra, int64_t extra_stride,
+                    T* out, int J, int K, int nrhs);
+// Multigrid work space for `rows` slabs: per level l, x[l] and b[l] (l < K)
+// and the residual r[l] (l >= 2); x[K] holds the iterate when write_Ax.
+template <typename T>
+struct Mg3Work {
+  T* x[kMaxK3 + 1] = {};
+  T* b[kMaxK3 + 1] = {};
+  T* r[kMaxK3 + 1] = {};
+};
+// x = K[a, sigma] b (vcycles V-cycles from zero) on `rows` slabs of level K,
+// or A_x of it when write_Ax; x must not alias b.
+template <typename T>
+hipError_t mg3_apply(hipStream_t s, const Mg3Work<T>& w, const T* b, T* x, int K, int rows,
+                     double a, const double* sigma, int vcycles, bool write_Ax);
 
 // ---- nested iteration (Section 4.2).
 // Data on a coarser mesh: dst (nrhs x rows_c slabs of level Kf - d) takes

@@ -107,8 +107,8 @@ template <typename T, bool UPD>
 __global__ __launch_bounds__(kBlock) void wavelet_syn_kernel(const T* src, T* dst, T* p,
                                                              const T* __restrict__ z,
                                                              const double* __restrict__ beta,
-                                                             int J, int K) {
-  const int64_t slab = slab_elems(K);
+                                                             int J, int64_t slab_) {
+  const int64_t slab = slab_;
   const int64_t col = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (col >= slab) return;
   const int N = 1 << J;
@@ -162,8 +162,8 @@ template <typename T, bool DOT>
 __global__ __launch_bounds__(kBlock) void wavelet_ana_kernel(T* __restrict__ X,
                                                              const T* __restrict__ p,
                                                              double* __restrict__ partials,
-                                                             int J, int K) {
-  const int64_t slab = slab_elems(K);
+                                                             int J, int64_t slab_) {
+  const int64_t slab = slab_;
   const int64_t col = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int N = 1 << J;
   const int64_t off = (int64_t)blockIdx.y * (N + 1) * slab + col;
@@ -257,12 +257,12 @@ template <typename T, bool UPD, int JMAX>
 __global__ __launch_bounds__(kLdsThreads) void wavelet_syn_lds_kernel(const T* src, T* dst, T* p,
                                                                       const T* __restrict__ z,
                                                                       const double* __restrict__ beta,
-                                                                      int J, int K) {
+                                                                      int J, int64_t slab_) {
   constexpr int C = lds_cols<T>();
   constexpr int RG = kLdsThreads / C;  // threads per column
   constexpr int B = UPD ? kBatch / 2 : kBatch;  // two loads per row with UPD
   __shared__ T sh[((1 << JMAX) + 1) * C];
-  const int64_t slab = slab_elems(K);
+  const int64_t slab = slab_;
   const int N = 1 << J;
   const int c = threadIdx.x % C, g = threadIdx.x / C;
   const double bt = UPD ? beta[blockIdx.y] : 0.0;
@@ -351,12 +351,12 @@ template <typename T, bool DOT, int JMAX>
 __global__ __launch_bounds__(kLdsThreads) void wavelet_ana_lds_kernel(T* __restrict__ X,
                                                                       const T* __restrict__ p,
                                                                       double* __restrict__ partials,
-                                                                      int J, int K) {
+                                                                      int J, int64_t slab_) {
   constexpr int C = lds_cols<T>();
   constexpr int RG = kLdsThreads / C;
   constexpr int BS = DOT ? kBatch / 2 : kBatch;  // two loads per row with DOT
   __shared__ T sh[((1 << JMAX) + 1) * C];
-  const int64_t slab = slab_elems(K);
+  const int64_t slab = slab_;
   const int N = 1 << J;
   const int c = threadIdx.x % C, g = threadIdx.x / C;
   const int64_t groups = (slab + C - 1) / C;
@@ -864,8 +864,8 @@ hipError_t apply_M(hipStream_t s, const T* x, T* y, int K, int rows) {
 
 // Workgroups of the LDS-resident transform per right-hand side.
 template <typename T>
-int lds_grid(int K) {
-  const int64_t groups = (slab_elems(K) + lds_cols<T>() - 1) / lds_cols<T>();
+int lds_grid(int64_t slab) {
+  const int64_t groups = (slab + lds_cols<T>() - 1) / lds_cols<T>();
   return (int)std::min<int64_t>(groups, kLdsGrid);
 }
 
@@ -874,77 +874,77 @@ int lds_grid(int K) {
 // otherwise.  In FP32 the column kernels measured as fast or faster.
 template <typename T, bool UPD>
 hipError_t launch_syn(hipStream_t s, const T* src, T* dst, T* p, const T* z, const double* beta,
-                      int J, int K, int nrhs) {
+                      int J, int64_t slab, int nrhs) {
   if constexpr (sizeof(T) == 8) {
     if (J <= kLdsJMax) {
-      const dim3 grid(lds_grid<T>(K), nrhs);
+      const dim3 grid(lds_grid<T>(slab), nrhs);
       if (J <= 8)
-        wavelet_syn_lds_kernel<T, UPD, 8><<<grid, kLdsThreads, 0, s>>>(src, dst, p, z, beta, J, K);
+        wavelet_syn_lds_kernel<T, UPD, 8><<<grid, kLdsThreads, 0, s>>>(src, dst, p, z, beta, J, slab);
       else if (J == 9)
-        wavelet_syn_lds_kernel<T, UPD, 9><<<grid, kLdsThreads, 0, s>>>(src, dst, p, z, beta, J, K);
+        wavelet_syn_lds_kernel<T, UPD, 9><<<grid, kLdsThreads, 0, s>>>(src, dst, p, z, beta, J, slab);
       else
         wavelet_syn_lds_kernel<T, UPD, 10><<<grid, kLdsThreads, 0, s>>>(src, dst, p, z, beta, J,
-                                                                        K);
+                                                                        slab);
       return hipGetLastError();
     }
   }
-  const dim3 grid(blocks_for(slab_elems(K)), nrhs);
-  wavelet_syn_kernel<T, UPD><<<grid, kBlock, 0, s>>>(src, dst, p, z, beta, J, K);
+  const dim3 grid(blocks_for(slab), nrhs);
+  wavelet_syn_kernel<T, UPD><<<grid, kBlock, 0, s>>>(src, dst, p, z, beta, J, slab);
   return hipGetLastError();
 }
 
 // Analysis launch; returns the number of partial sums per right-hand side
 // (with DOT) through nblk.
 template <typename T, bool DOT>
-hipError_t launch_ana(hipStream_t s, T* X, const T* p, double* partials, int J, int K, int nrhs,
+hipError_t launch_ana(hipStream_t s, T* X, const T* p, double* partials, int J, int64_t slab, int nrhs,
                       int* nblk) {
   if constexpr (sizeof(T) == 8) {
     if (J <= kLdsJMax) {
-      const dim3 grid(lds_grid<T>(K), nrhs);
+      const dim3 grid(lds_grid<T>(slab), nrhs);
       *nblk = (int)grid.x;
       if (J <= 8)
-        wavelet_ana_lds_kernel<T, DOT, 8><<<grid, kLdsThreads, 0, s>>>(X, p, partials, J, K);
+        wavelet_ana_lds_kernel<T, DOT, 8><<<grid, kLdsThreads, 0, s>>>(X, p, partials, J, slab);
       else if (J == 9)
-        wavelet_ana_lds_kernel<T, DOT, 9><<<grid, kLdsThreads, 0, s>>>(X, p, partials, J, K);
+        wavelet_ana_lds_kernel<T, DOT, 9><<<grid, kLdsThreads, 0, s>>>(X, p, partials, J, slab);
       else
-        wavelet_ana_lds_kernel<T, DOT, 10><<<grid, kLdsThreads, 0, s>>>(X, p, partials, J, K);
+        wavelet_ana_lds_kernel<T, DOT, 10><<<grid, kLdsThreads, 0, s>>>(X, p, partials, J, slab);
       return hipGetLastError();
     }
   }
-  const dim3 grid(blocks_for(slab_elems(K)), nrhs);
+  const dim3 grid(blocks_for(slab), nrhs);
   *nblk = (int)grid.x;
-  wavelet_ana_kernel<T, DOT><<<grid, kBlock, 0, s>>>(X, p, partials, J, K);
+  wavelet_ana_kernel<T, DOT><<<grid, kBlock, 0, s>>>(X, p, partials, J, slab);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t wavelet(hipStream_t s, T* X, int J, int K, int nrhs, bool synthesis) {
+hipError_t wavelet(hipStream_t s, T* X, int J, int64_t slab, int nrhs, bool synthesis) {
   if (J == 0) return hipSuccess;
-  if (synthesis) return launch_syn<T, false>(s, X, X, nullptr, nullptr, nullptr, J, K, nrhs);
+  if (synthesis) return launch_syn<T, false>(s, X, X, nullptr, nullptr, nullptr, J, slab, nrhs);
   int nblk = 0;
-  return launch_ana<T, false>(s, X, nullptr, nullptr, J, K, nrhs, &nblk);
+  return launch_ana<T, false>(s, X, nullptr, nullptr, J, slab, nrhs, &nblk);
 }
 
 template <typename T>
-hipError_t synthesis(hipStream_t s, const T* src, T* dst, int J, int K, int nrhs) {
-  return launch_syn<T, false>(s, src, dst, nullptr, nullptr, nullptr, J, K, nrhs);
+hipError_t synthesis(hipStream_t s, const T* src, T* dst, int J, int64_t slab, int nrhs) {
+  return launch_syn<T, false>(s, src, dst, nullptr, nullptr, nullptr, J, slab, nrhs);
 }
 
 template <typename T>
 hipError_t synthesis_update(hipStream_t s, T* p, const T* z, const double* beta, T* X, int J,
-                            int K, int nrhs) {
-  return launch_syn<T, true>(s, p, X, p, z, beta, J, K, nrhs);
+                            int64_t slab, int nrhs) {
+  return launch_syn<T, true>(s, p, X, p, z, beta, J, slab, nrhs);
 }
 
-int analysis_dot_blocks(int K) {
-  return (int)std::max<int64_t>(blocks_for(slab_elems(K)), kLdsGrid);
+int analysis_dot_blocks(int64_t slab) {
+  return (int)std::max<int64_t>(blocks_for(slab), kLdsGrid);
 }
 
 template <typename T>
 hipError_t analysis_dot(hipStream_t s, T* X, const T* p, double* partials, double* out, int J,
-                        int K, int nrhs) {
+                        int64_t slab, int nrhs) {
   int nblk = 0;
-  const hipError_t e = launch_ana<T, true>(s, X, p, partials, J, K, nrhs, &nblk);
+  const hipError_t e = launch_ana<T, true>(s, X, p, partials, J, slab, nrhs, &nblk);
   if (e != hipSuccess) return e;
   dot_final_kernel<<<nrhs, kBlock, 0, s>>>(partials, nblk, out);
   return hipGetLastError();
@@ -1091,11 +1091,13 @@ hipError_t fill_level_sigma(hipStream_t s, double* sigma, int J, int nrhs) {
 #define STP_INSTANTIATE(T)                                                                        \
   template hipError_t apply_A<T>(hipStream_t, const T*, T*, int, int, const SpaceOp&);            \
   template hipError_t apply_M<T>(hipStream_t, const T*, T*, int, int);                            \
-  template hipError_t wavelet<T>(hipStream_t, T*, int, int, int, bool);                           \
-  template hipError_t synthesis<T>(hipStream_t, const T*, T*, int, int, int);                     \
-  template hipError_t synthesis_update<T>(hipStream_t, T*, const T*, const double*, T*, int, int, \
+  template hipError_t wavelet<T>(hipStream_t, T*, int, int64_t, int, bool);                       \
+  template hipError_t synthesis<T>(hipStream_t, const T*, T*, int, int64_t, int);                 \
+  template hipError_t synthesis_update<T>(hipStream_t, T*, const T*, const double*, T*, int,      \
+                                          int64_t,                                                \
                                           int);                                                  \
-  template hipError_t analysis_dot<T>(hipStream_t, T*, const T*, double*, double*, int, int, int); \
+  template hipError_t analysis_dot<T>(hipStream_t, T*, const T*, double*, double*, int, int64_t, \
+                                      int);                                                       \
   template hipError_t dot<T>(hipStream_t, const T*, const T*, int64_t, int, double*, double*);    \
   template hipError_t copy<T>(hipStream_t, const T*, T*, int64_t);                                \
   template hipError_t update_wr<T>(hipStream_t, T*, T*, const T*, const T*, const double*,        \

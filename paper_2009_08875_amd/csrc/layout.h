@@ -16,11 +16,20 @@ namespace stp {
 
 inline constexpr int kMaxJ = 14;
 inline constexpr int kMaxK = 10;
+inline constexpr int kMaxK3 = 8;  // three space dimensions
 
 __host__ __device__ inline int grid_n(int l) { return (1 << l) - 1; }
 __host__ __device__ inline int line_pitch(int l) { return 1 << l; }
 __host__ __device__ inline int64_t slab_elems(int l) {
   int64_t e = (int64_t)grid_n(l) * line_pitch(l);
+  return (e + 63) & ~(int64_t)63;
+}
+
+// Three space dimensions (the unit cube): a slab stores the n_l^3 interior
+// nodes plane by plane and line by line with line pitch 2^l: node (a, b, c)
+// at ((c - 1) n_l + (b - 1)) 2^l + (a - 1); rounded up to 64 elements.
+__host__ __device__ inline int64_t slab3_elems(int l) {
+  int64_t e = (int64_t)grid_n(l) * grid_n(l) * line_pitch(l);
   return (e + 63) & ~(int64_t)63;
 }
 

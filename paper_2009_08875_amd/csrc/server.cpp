@@ -346,8 +346,9 @@ stp_status stp_server_create(size_t hbm_budget_bytes, int max_slots, int max_bat
               "and 1 <= max_batch <= 64");
     return STP_E_INVALID_ARG;
   }
-  if (opt && opt->nested > 0) {
-    set_error("stp_server_create: nested iteration is not offered by the server");
+  if (opt && (opt->nested > 0 || opt->dim == 3)) {
+    set_error("stp_server_create: nested iteration and the 3D problem are not offered by the "
+              "server");
     return STP_E_UNSUPPORTED;
   }
   *out = nullptr;

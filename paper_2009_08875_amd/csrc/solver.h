@@ -45,7 +45,8 @@ struct Ops {
   T* X = nullptr;      // nodal W p                                  (vec)
   T* y = nullptr;      // y1 | y2                                    (2 vec)
   T* z = nullptr;      // K_x y1 | K_x y2                            (2 vec)
-  MgScratch<T> mg;
+  MgScratch<T> mg;     // two space dimensions
+  Mg3Work<T> mg3;      // three space dimensions (mg.chunk_rows rows per level)
 };
 
 template <typename T>
@@ -58,6 +59,8 @@ struct PcgVecs {
 
 struct stp_ctx {
   int J = 0, K = 0, nrhs = 1, prec = STP_FP64;
+  int dim = 2;             // space dimensions: 2 (unit square) or 3 (unit cube)
+  int64_t nx = 0;          // interior nodes per time row, (2^K - 1)^dim
   stp_options opt{};
   stp::SpaceOp op;          // A_x = A_D + c M_x (Section 4); the heat equation by default
   int device = 0;

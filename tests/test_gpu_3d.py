@@ -1,0 +1,162 @@
+"""The 3D heat equation of Section 5.2 on the GPU against the oracle
+(oracle/space3d.py): the unit cube on the Kuhn tetrahedral mesh, the same
+space-time method (Lemma 4.2's S with K_x, the wavelet-in-time system,
+K_X of Theorem 3.1) with the 3D stiffness, mass and four-colour multigrid.
+
+Every operator through stp_apply (FP64 1e-12, FP32 2e-4), solves by the
+fixed-iteration protocol (1e-10) and converged in the mixed form (1e-6),
+Section 5.2's test solution exp(-3 pi^2 t) sin(pi x) sin(pi y) sin(pi z)
+with g = 0, a batch equal to its solo solves, and the refused requests."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle.schur import Problem
+from tests.gpu_helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def stp():
+    import paper_2009_08875_amd as lib
+
+    return lib
+
+
+D3 = {"dim": 3}
+
+
+def flat(x):
+    return np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+
+
+def _oracle_op(P, name, X):
+    return {"W": P.W, "WT": P.WT, "S": P.S, "SHAT": P.Shat, "KX": P.KX, "KSPACE": P.Kx,
+            "A": P.A, "M": P.M}[name](X)
+
+
+def _max_rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("J,K", [(2, 3), (1, 4), (3, 1), (0, 2)])
+@pytest.mark.parametrize("prec", ["FP64", "MIXED"])
+def test_operators_3d(stp, J, K, prec):
+    P = Problem(J, K, dim=3)
+    X = synth.random_field(P.shape, 500 + J * 16 + K)
+    p = getattr(stp, "STP_" + prec)
+    ctx = stp.stp_create(J, K, 1, p, D3)
+    try:
+        for name in ["W", "WT", "A", "M", "KSPACE", "KX", "S", "SHAT"]:
+            out = np.zeros(X.size)
+            stp.stp_apply(ctx, getattr(stp, "STP_OP_" + name), p, 0, flat(X), out)
+            err = _max_rel(out.reshape(P.shape), _oracle_op(P, name, X))
+            say(f"3D J={J} K={K} {prec} {name}: {err:.2e}")
+            assert err <= (1e-12 if prec == "FP64" else 2e-4), name
+    finally:
+        stp.stp_destroy(ctx)
+
+
+def test_rhs_3d(stp):
+    J, K = 2, 3
+    P = Problem(J, K, dim=3)
+    rng = np.random.default_rng(9)
+    g, u0 = rng.standard_normal(P.shape), rng.standard_normal(P.shape[1:])
+    ctx = stp.stp_create(J, K, 1, stp.STP_FP64, D3)
+    try:
+        stp.stp_set_g(ctx, 0, flat(g))
+        stp.stp_set_u0(ctx, 0, flat(u0))
+        out = np.zeros(g.size)
+        stp.stp_apply(ctx, stp.STP_OP_RHS, stp.STP_FP64, 0, None, out)
+    finally:
+        stp.stp_destroy(ctx)
+    assert _max_rel(out.reshape(P.shape), P.rhs(g, u0)) <= 1e-12
+
+
+def _cube_sin(K):
+    n = 2 ** K - 1
+    s = np.sin(np.pi * np.arange(1, n + 1) / 2 ** K)
+    return np.einsum("i,j,k->kji", s, s, s)
+
+
+def _solve(stp, J, K, prec, opts, g, u0, tol, nrhs=1):
+    ctx = stp.stp_create(J, K, nrhs, prec, opts)
+    try:
+        for b in range(nrhs):
+            stp.stp_set_g(ctx, b, None if g is None else flat(g[b] if nrhs > 1 else g))
+            stp.stp_set_u0(ctx, b, flat(u0[b] if nrhs > 1 else u0))
+        status, st = stp.stp_solve(ctx, tol, nrhs=nrhs)
+        us = []
+        for b in range(nrhs):
+            u = np.zeros((2 ** J + 1) * (2 ** K - 1) ** 3)
+            stp.stp_get_solution(ctx, b, u)
+            us.append(u.reshape((2 ** J + 1,) + (2 ** K - 1,) * 3))
+    finally:
+        stp.stp_destroy(ctx)
+    return status, st, us
+
+
+@pytest.mark.parametrize("J,K,forcing", [(3, 3, False), (2, 4, True)])
+def test_solves_3d(stp, J, K, forcing):
+    rng = np.random.default_rng(J + 10 * K)
+    P = Problem(J, K, dim=3)
+    g = rng.standard_normal(P.shape) if forcing else None
+    u0 = _cube_sin(K)
+    u_or, k_or, _ = oracle.solve(J, K, g, u0, tol=1e-8, dim=3)
+    status, st, u = _solve(stp, J, K, stp.STP_FP64, dict(D3, maxit=k_or), g, u0, 0.0)
+    err64 = rel_err(u[0], u_or)
+    u_or10, _, _ = oracle.solve(J, K, g, u0, tol=1e-10, dim=3)
+    status_m, st_m, um = _solve(stp, J, K, stp.STP_MIXED, D3, g, u0, 1e-8)
+    errm = rel_err(um[0], u_or10)
+    say(f"3D J={J} K={K}: oracle its {k_or}; FP64 fixed-its {err64:.2e}; mixed "
+        f"{st_m[0]['iterations']}/{st_m[0]['outer_iterations']} {errm:.2e}")
+    assert status == stp.STP_OK and st[0]["iterations"] == k_or and err64 <= 1e-10
+    assert status_m == stp.STP_OK and errm <= 1e-6
+
+
+def test_exact_solution_3d(stp):
+    """Section 5.2's solution: the nodal error at J = K = 4 is below the
+    oracle's bound for this mesh and matches the oracle's solution."""
+    J = K = 4
+    u0 = _cube_sin(K)
+    status, st, u = _solve(stp, J, K, stp.STP_FP64, D3, None, u0, 1e-10)
+    u_or, _, _ = oracle.solve(J, K, None, u0, tol=1e-10, dim=3)
+    t = np.arange(2 ** J + 1) / 2 ** J
+    exact = np.exp(-3 * np.pi ** 2 * t)[:, None, None, None] * u0[None]
+    err = np.abs(u[0] - exact).max()
+    say(f"3D J=K=4: {st[0]['iterations']} iterations, nodal error vs exact {err:.3e}, "
+        f"vs oracle {rel_err(u[0], u_or):.2e}")
+    assert status == stp.STP_OK and err <= 0.13 and rel_err(u[0], u_or) <= 1e-8
+
+
+def test_batched_equals_solo_3d(stp):
+    J, K, B = 2, 3, 3
+    P = Problem(J, K, dim=3)
+    rng = np.random.default_rng(77)
+    g = [rng.standard_normal(P.shape) for _ in range(B)]
+    u0 = [rng.standard_normal(P.shape[1:]) for _ in range(B)]
+    status, st, ub = _solve(stp, J, K, stp.STP_FP64, D3, g, u0, 1e-8, nrhs=B)
+    assert status == stp.STP_OK
+    for b in range(B):
+        s1, st1, u1 = _solve(stp, J, K, stp.STP_FP64, D3, g[b], u0[b], 1e-8)
+        assert st1[0]["iterations"] == st[b]["iterations"]
+        assert np.array_equal(u1[0], ub[b])
+
+
+def test_3d_refused_requests(stp):
+    with pytest.raises(stp.StpError) as e:
+        stp.stp_create(2, 9, 1, stp.STP_FP64, D3)
+    assert e.value.status == stp.STP_E_INVALID_ARG
+    for opts in (dict(D3, nested=1), dict(D3, reaction=1.0)):
+        with pytest.raises(stp.StpError) as e:
+            stp.stp_create(2, 3, 1, stp.STP_FP64, opts)
+        assert e.value.status == stp.STP_E_UNSUPPORTED
