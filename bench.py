@@ -27,6 +27,10 @@ WORKLOADS = {
     "heat2d_J12_K9": (12, 9, 1, 2, "sin"),
     "heat2d_J8_K7_B64": (8, 7, 64, 1000, "random4"),
     "heat2d_J4_K4": (4, 4, 1, None, "sin"),
+    # the 3D problem (unit cube, Kuhn mesh) at the shape of the paper's 3D weak
+    # scaling row with N_t = 257 time nodes and N_x = 250047: g = 0,
+    # u0 = sin(pi x) sin(pi y) sin(pi z)
+    "heat3d_J8_K6": (8, 6, 1, None, "sin3"),
     # request stream of uneven sizes (J in 6..11, K in 5..9), see run_serving
     "heat2d_serve": None,
 }
@@ -75,6 +79,8 @@ def load_inputs(stp, ctx, J, K, nrhs, seed, u0kind, torch):
             del g
         if u0kind == "sin":
             u0 = synth.sine_product(K, 1, 1)
+        elif u0kind == "sin3":
+            u0 = synth.sine_product_3d(K)
         else:
             u0 = synth.smooth_u0(K, seed + b)
         stp.stp_set_u0(ctx, b, u0.reshape(-1).copy())
@@ -399,11 +405,13 @@ def main():
 
     J, K, nrhs, seed, u0kind = WORKLOADS[args.workload]
     prec = stp.STP_FP64 if args.precision == "fp64" else stp.STP_MIXED
-    unknowns = (2 ** J + 1) * (2 ** K - 1) ** 2 * nrhs
+    dim = 3 if u0kind == "sin3" else 2
+    opts = {"dim": 3} if dim == 3 else None
+    unknowns = (2 ** J + 1) * (2 ** K - 1) ** dim * nrhs
     print(f"# workload {args.workload} J={J} K={K} nrhs={nrhs} precision={args.precision}",
           file=sys.stderr, flush=True)
 
-    ctx = stp.stp_create(J, K, nrhs, prec, stream=torch.cuda.current_stream())
+    ctx = stp.stp_create(J, K, nrhs, prec, opts, stream=torch.cuda.current_stream())
     load_inputs(stp, ctx, J, K, nrhs, seed, u0kind, torch)
     t_step, stats = run_solves(stp, ctx, nrhs, args.tol, args.steps, args.warmup, torch)
     kst = profile_solve(stp, ctx, nrhs, args.tol, torch)
@@ -439,7 +447,7 @@ def main():
     compare = None
     if not args.no_compare:
         other = stp.STP_MIXED if prec == stp.STP_FP64 else stp.STP_FP64
-        ctx = stp.stp_create(J, K, nrhs, other, stream=torch.cuda.current_stream())
+        ctx = stp.stp_create(J, K, nrhs, other, opts, stream=torch.cuda.current_stream())
         load_inputs(stp, ctx, J, K, nrhs, seed, u0kind, torch)
         t2, st2 = run_solves(stp, ctx, nrhs, args.tol, 2, 1, torch)
         u2 = torch.zeros_like(u_main)
@@ -479,7 +487,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == stp.STP_FP64 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "J": J, "K": K, "nrhs": nrhs,
+        "config": {"workload": args.workload, "J": J, "K": K, "nrhs": nrhs, "dim": dim,
                    "unknowns": unknowns, "precision": args.precision, "rel_tol": args.tol,
                    "iterations": its, "time_to_solve_s": round(t_step, 4),
                    "parallelism": "single-gpu"},

@@ -39,6 +39,13 @@ def sine_product(K: int, k: int = 1, l: int = 1) -> np.ndarray:
     return np.outer(np.sin(l * np.pi * x), np.sin(k * np.pi * x))
 
 
+def sine_product_3d(K: int) -> np.ndarray:
+    """Nodal values of ``sin(pi x) sin(pi y) sin(pi z)`` on the interior nodes of
+    the unit cube, shape (n, n, n) indexed [k, j, i] (z slowest)."""
+    s = np.sin(np.pi * nodes_1d(K))
+    return np.einsum("i,j,k->kji", s, s, s)
+
+
 def fourier_coefficients(seed: int, kmax: int = KMAX) -> np.ndarray:
     """Coefficients ``c[k-1, l-1, m]`` of the forcing
     ``g = sum c_klm sin(k pi x) sin(l pi y) cos(m pi t)``,
