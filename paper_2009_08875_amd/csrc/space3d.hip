@@ -8,10 +8,10 @@
 // (1, 0, 1), (0, 1, 1)), the sums of the element matrices of the 24
 // tetrahedra around a node.
 //
-// Kernels run one thread per slab element and time row (a grid-stride loop
-// over the rows).  Neighbour values come straight from global memory, which
-// the L2 caches; these kernels are written for correctness and a clear
-// structure, not tiled like the two-dimensional ones.
+// Kernels run one 64-lane wave per grid line (j, k) and time row (a
+// grid-stride loop over the rows).  Neighbour values come straight from
+// global memory, which the L2 caches; there is no LDS tiling as in the
+// two-dimensional kernels.
 //
 // Multigrid (K_x and the K_l of Theorem 3.1, Section 5.1's two V-cycles with
 // three Gauss-Seidel steps per grid): the colours (i + j + k) mod 4 -- the
@@ -30,122 +30,143 @@ namespace stp {
 
 namespace {
 
-constexpr int kBlock3 = 256;
 constexpr int kMaxGridRows = 65535;
 
-// the 15 mass offsets: the node, +- the seven edge directions
-__constant__ int kOff[15][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},  {0, -1, 0},
-                               {0, 0, 1},  {0, 0, -1},  {1, 1, 0},   {-1, -1, 0}, {1, 0, 1},
-                               {-1, 0, -1}, {0, 1, 1},   {0, -1, -1}, {1, 1, 1},  {-1, -1, -1}};
+// Launch geometry: one 64-lane wave per grid line (j, k) of a slab and per
+// time row (grid-stride over rows); lane t takes the line's nodes
+// i = i0 + t * stride.  The line's position is uniform across the wave, so a
+// node's 14 neighbours sit in 9 line offsets computed once per wave, and the
+// lanes only check i against the grid.
+constexpr int kLane = 64;
 
-struct Node3 {
-  int i, j, k;  // 1-based
+struct Line3 {
+  int j, k, n, pitch;
+  int64_t off;  // slab offset of node (1, j, k)
 };
 
-__device__ __forceinline__ bool node3_of(int64_t idx, int l, Node3& p) {
-  const int n = grid_n(l), pitch = line_pitch(l);
-  const int64_t line = idx / pitch;
-  p.i = (int)(idx - line * pitch) + 1;
-  p.j = (int)(line % n) + 1;
-  p.k = (int)(line / n) + 1;
-  return p.i <= n && p.k <= n;
+__device__ __forceinline__ Line3 line3(int line, int l) {
+  Line3 L;
+  L.n = grid_n(l);
+  L.pitch = line_pitch(l);
+  L.j = line % L.n + 1;
+  L.k = line / L.n + 1;
+  L.off = (int64_t)line * L.pitch;
+  return L;
 }
 
-template <typename T>
-__device__ __forceinline__ T at3(const T* s, int l, int i, int j, int k) {
-  const int n = grid_n(l);
-  if (i < 1 || i > n || j < 1 || j > n || k < 1 || k > n) return T(0);
-  return s[((int64_t)(k - 1) * n + (j - 1)) * line_pitch(l) + (i - 1)];
+// value of slab s at node (i + di, j + dj, k + dk) of the line, zero outside
+template <typename T, int DI, int DJ, int DK>
+__device__ __forceinline__ T nb3(const T* s, const Line3& L, int i) {
+  const int ii = i + DI, jj = L.j + DJ, kk = L.k + DK;
+  if (ii < 1 || ii > L.n || jj < 1 || jj > L.n || kk < 1 || kk > L.n) return T(0);
+  return s[L.off + ((int64_t)DK * L.n + DJ) * L.pitch + (ii - 1)];
 }
 
-// Stencil weights of C = a A_x + sigma M_x on level l, by offset index of kOff.
+// Stencil weights of C = a A_x + sigma M_x on level l: centre, the six axis
+// neighbours, the six face-diagonal and the two body-diagonal neighbours.
 struct C3 {
-  double w[15];
+  double c0, ax, fd, bd;
 };
 __device__ __forceinline__ C3 coef3(double a, double sigma, int l) {
   const double h = 1.0 / (double)(1 << l);
   const double m = sigma * h * h * h;
-  C3 c;
-  c.w[0] = a * 6.0 * h + 0.4 * m;
-  for (int q = 1; q <= 6; ++q) c.w[q] = -a * h + m / 20.0;
-  for (int q = 7; q <= 12; ++q) c.w[q] = m / 30.0;
-  c.w[13] = c.w[14] = m / 20.0;
-  return c;
+  return {a * 6.0 * h + 0.4 * m, -a * h + m / 20.0, m / 30.0, m / 20.0};
 }
 
-// sum_q w_q x(p + off_q) over the offsets [q0, q1)
 template <typename T>
-__device__ __forceinline__ T stencil3(const T* s, int l, const Node3& p, const C3& c, int q0,
-                                      int q1) {
-  T acc = T(0);
-  for (int q = q0; q < q1; ++q)
-    acc += T(c.w[q]) * at3(s, l, p.i + kOff[q][0], p.j + kOff[q][1], p.k + kOff[q][2]);
-  return acc;
+__device__ __forceinline__ T axis_sum(const T* s, const Line3& L, int i) {
+  return ((nb3<T, 1, 0, 0>(s, L, i) + nb3<T, -1, 0, 0>(s, L, i)) +
+          (nb3<T, 0, 1, 0>(s, L, i) + nb3<T, 0, -1, 0>(s, L, i))) +
+         (nb3<T, 0, 0, 1>(s, L, i) + nb3<T, 0, 0, -1>(s, L, i));
+}
+template <typename T>
+__device__ __forceinline__ T face_sum(const T* s, const Line3& L, int i) {
+  return ((nb3<T, 1, 1, 0>(s, L, i) + nb3<T, -1, -1, 0>(s, L, i)) +
+          (nb3<T, 1, 0, 1>(s, L, i) + nb3<T, -1, 0, -1>(s, L, i))) +
+         (nb3<T, 0, 1, 1>(s, L, i) + nb3<T, 0, -1, -1>(s, L, i));
+}
+template <typename T>
+__device__ __forceinline__ T body_sum(const T* s, const Line3& L, int i) {
+  return nb3<T, 1, 1, 1>(s, L, i) + nb3<T, -1, -1, -1>(s, L, i);
 }
 
-// thread -> (slab element, row) over a 2D grid, rows in a grid-stride loop
-#define FOR_ELEMS_3D(l, rows)                                                     \
-  const int64_t idx = (int64_t)blockIdx.x * kBlock3 + threadIdx.x;               \
-  if (idx >= slab3_elems(l)) return;                                               \
+// (C x) at node i of the line without (off-centre part) or with the centre;
+// DIAG: the mass couplings across the diagonals are present (sigma != 0).
+template <typename T, bool DIAG>
+__device__ __forceinline__ T off3(const T* s, const Line3& L, int i, const C3& c) {
+  T v = T(c.ax) * axis_sum(s, L, i);
+  if constexpr (DIAG) v += T(c.fd) * face_sum(s, L, i) + T(c.bd) * body_sum(s, L, i);
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T mass3(const T* s, const Line3& L, int i, const C3& c) {
+  return (T(c.c0) * nb3<T, 0, 0, 0>(s, L, i) + T(c.ax) * axis_sum(s, L, i)) +
+         (T(c.fd) * face_sum(s, L, i) + T(c.bd) * body_sum(s, L, i));
+}
+
+// grid: x = lines of the level (n^2), y = rows (grid-stride), one wave each
+inline dim3 grid3(int l, int rows) {
+  return dim3((unsigned)(grid_n(l) * grid_n(l)), (unsigned)std::min(rows, kMaxGridRows));
+}
+#define FOR_LINE_ROWS(l, rows)                    \
+  const Line3 L = line3(blockIdx.x, l);            \
   for (int row = blockIdx.y; row < (rows); row += gridDim.y)
 
-inline dim3 grid3(int l, int rows) {
-  return dim3((unsigned)((slab3_elems(l) + kBlock3 - 1) / kBlock3),
-              (unsigned)std::min(rows, kMaxGridRows));
+// writes the pads of a line (the element i = 2^l) and of the slab tail zero
+template <typename T>
+__device__ __forceinline__ void zero_pads(T* slab_base, const Line3& L, int l, int line) {
+  if (threadIdx.x == 0) slab_base[L.off + L.n] = T(0);
+  const int64_t used = (int64_t)L.n * L.n * L.pitch;
+  if (line == L.n * L.n - 1)
+    for (int64_t e = used + threadIdx.x; e < slab3_elems(l); e += kLane) slab_base[e] = T(0);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock3) void pack3_kernel(const double* __restrict__ src,
-                                                        T* __restrict__ dst, int K, int rows) {
+__global__ __launch_bounds__(kLane) void pack3_kernel(const double* __restrict__ src,
+                                                      T* __restrict__ dst, int K, int rows) {
   const int64_t nx = (int64_t)grid_n(K) * grid_n(K) * grid_n(K);
-  FOR_ELEMS_3D(K, rows) {
-    Node3 p;
-    T v = T(0);
-    if (node3_of(idx, K, p))
-      v = (T)src[row * nx + ((int64_t)(p.k - 1) * grid_n(K) + (p.j - 1)) * grid_n(K) + (p.i - 1)];
-    dst[row * slab3_elems(K) + idx] = v;
+  FOR_LINE_ROWS(K, rows) {
+    T* d = dst + row * slab3_elems(K);
+    const double* sr = src + row * nx + (int64_t)blockIdx.x * L.n;
+    for (int i = 1 + threadIdx.x; i <= L.n; i += kLane) d[L.off + i - 1] = (T)sr[i - 1];
+    zero_pads(d, L, K, blockIdx.x);
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock3) void unpack3_kernel(const T* __restrict__ src,
-                                                          double* __restrict__ dst, int K,
-                                                          int rows) {
+__global__ __launch_bounds__(kLane) void unpack3_kernel(const T* __restrict__ src,
+                                                        double* __restrict__ dst, int K,
+                                                        int rows) {
   const int64_t nx = (int64_t)grid_n(K) * grid_n(K) * grid_n(K);
-  FOR_ELEMS_3D(K, rows) {
-    Node3 p;
-    if (!node3_of(idx, K, p)) continue;
-    dst[row * nx + ((int64_t)(p.k - 1) * grid_n(K) + (p.j - 1)) * grid_n(K) + (p.i - 1)] =
-        (double)src[row * slab3_elems(K) + idx];
+  FOR_LINE_ROWS(K, rows) {
+    const T* s = src + row * slab3_elems(K);
+    double* dr = dst + row * nx + (int64_t)blockIdx.x * L.n;
+    for (int i = 1 + threadIdx.x; i <= L.n; i += kLane) dr[i - 1] = (double)s[L.off + i - 1];
   }
 }
 
 // y = (a A + sigma M) x per row (A: a = 1, sigma = 0; M: a = 0, sigma = 1)
 template <typename T>
-__global__ __launch_bounds__(kBlock3) void apply3_kernel(const T* __restrict__ x,
-                                                         T* __restrict__ y, int K, int rows,
-                                                         double a, double sigma) {
+__global__ __launch_bounds__(kLane) void apply3_kernel(const T* __restrict__ x,
+                                                       T* __restrict__ y, int K, int rows,
+                                                       double a, double sigma) {
   const C3 c = coef3(a, sigma, K);
-  FOR_ELEMS_3D(K, rows) {
-    Node3 p;
-    T v = T(0);
-    if (node3_of(idx, K, p)) v = stencil3(x + row * slab3_elems(K), K, p, c, 0, 15);
-    y[row * slab3_elems(K) + idx] = v;
+  FOR_LINE_ROWS(K, rows) {
+    const T* xr = x + row * slab3_elems(K);
+    T* yr = y + row * slab3_elems(K);
+    for (int i = 1 + threadIdx.x; i <= L.n; i += kLane) yr[L.off + i - 1] = mass3(xr, L, i, c);
+    zero_pads(yr, L, K, blockIdx.x);
   }
 }
 
-// The four time combinations of Lemma 4.2 at a node of row i (exact hat
-// integrals, one-sided at t = 0 and t = 1).
+// The four time combinations of Lemma 4.2 of one node value in rows
+// i - 1, i, i + 1 (exact hat integrals, one-sided at t = 0 and t = 1).
 template <typename T>
 struct TC3 {
   T At, Mt, L, LT;
 };
 template <typename T>
-__device__ __forceinline__ TC3<T> tc3(const T* X, int64_t base, int64_t slab, int i, int N, int K,
-                                      int a, int b, int c) {
-  const T x0 = at3(X + base + (int64_t)i * slab, K, a, b, c);
-  const T xm = i > 0 ? at3(X + base + (int64_t)(i - 1) * slab, K, a, b, c) : T(0);
-  const T xp = i < N ? at3(X + base + (int64_t)(i + 1) * slab, K, a, b, c) : T(0);
+__device__ __forceinline__ TC3<T> tc_of(T xm, T x0, T xp, int i, int N) {
   const T inv_tau = T((double)N), tau6 = T(1.0 / (6.0 * (double)N));
   TC3<T> r;
   if (i == 0) {
@@ -169,24 +190,25 @@ __device__ __forceinline__ TC3<T> tc3(const T* X, int64_t base, int64_t slab, in
 
 // MODE 0: y1 = M (A_t X) + A (L^T X), y2 = A (M_t X) + M (L X)
 // MODE 1: G1 = M (L^T g), G0 = M (M_t g)
+// Each output node needs the time combinations at its 15 mass neighbours;
+// they are formed from the three time rows on the fly.
 template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock3) void time_pair3_kernel(const T* __restrict__ X,
-                                                             T* __restrict__ y1,
-                                                             T* __restrict__ y2, int J, int K,
-                                                             int rows) {
+__global__ __launch_bounds__(kLane) void time_pair3_kernel(const T* __restrict__ X,
+                                                           T* __restrict__ y1,
+                                                           T* __restrict__ y2, int J, int K,
+                                                           int rows) {
   const int N = 1 << J;
   const int64_t slab = slab3_elems(K);
   const C3 ca = coef3(1.0, 0.0, K), cm = coef3(0.0, 1.0, K);
-  FOR_ELEMS_3D(K, rows) {
-    Node3 p;
-    T o1 = T(0), o2 = T(0);
-    if (node3_of(idx, K, p)) {
-      const int rhs = row / (N + 1), i = row - rhs * (N + 1);
-      const int64_t base = (int64_t)rhs * (N + 1) * slab;
-      for (int q = 0; q < 15; ++q) {
-        const TC3<T> t =
-            tc3(X, base, slab, i, N, K, p.i + kOff[q][0], p.j + kOff[q][1], p.k + kOff[q][2]);
-        const T wm = T(cm.w[q]), wa = T(ca.w[q]);
+  FOR_LINE_ROWS(K, rows) {
+    const int rhs = row / (N + 1), ti = row - rhs * (N + 1);
+    const T* x0 = X + (int64_t)row * slab;
+    const T* xm = ti > 0 ? x0 - slab : nullptr;
+    const T* xp = ti < N ? x0 + slab : nullptr;
+    for (int i = 1 + threadIdx.x; i <= L.n; i += kLane) {
+      T o1 = T(0), o2 = T(0);
+      auto add = [&](auto nbf, T wm, T wa) {
+        const TC3<T> t = tc_of(xm ? nbf(xm) : T(0), nbf(x0), xp ? nbf(xp) : T(0), ti, N);
         if constexpr (MODE == 0) {
           o1 += wm * t.At + wa * t.LT;
           o2 += wa * t.Mt + wm * t.L;
@@ -194,104 +216,139 @@ __global__ __launch_bounds__(kBlock3) void time_pair3_kernel(const T* __restrict
           o1 += wm * t.LT;
           o2 += wm * t.Mt;
         }
-      }
+      };
+#define STP_NB(DI, DJ, DK) [&](const T* s) { return nb3<T, DI, DJ, DK>(s, L, i); }
+      add(STP_NB(0, 0, 0), T(cm.c0), T(ca.c0));
+      add(STP_NB(1, 0, 0), T(cm.ax), T(ca.ax));
+      add(STP_NB(-1, 0, 0), T(cm.ax), T(ca.ax));
+      add(STP_NB(0, 1, 0), T(cm.ax), T(ca.ax));
+      add(STP_NB(0, -1, 0), T(cm.ax), T(ca.ax));
+      add(STP_NB(0, 0, 1), T(cm.ax), T(ca.ax));
+      add(STP_NB(0, 0, -1), T(cm.ax), T(ca.ax));
+      add(STP_NB(1, 1, 0), T(cm.fd), T(0));
+      add(STP_NB(-1, -1, 0), T(cm.fd), T(0));
+      add(STP_NB(1, 0, 1), T(cm.fd), T(0));
+      add(STP_NB(-1, 0, -1), T(cm.fd), T(0));
+      add(STP_NB(0, 1, 1), T(cm.fd), T(0));
+      add(STP_NB(0, -1, -1), T(cm.fd), T(0));
+      add(STP_NB(1, 1, 1), T(cm.bd), T(0));
+      add(STP_NB(-1, -1, -1), T(cm.bd), T(0));
+#undef STP_NB
+      y1[(int64_t)row * slab + L.off + i - 1] = o1;
+      y2[(int64_t)row * slab + L.off + i - 1] = o2;
     }
-    y1[row * slab + idx] = o1;
-    y2[row * slab + idx] = o2;
+    zero_pads(y1 + (int64_t)row * slab, L, K, blockIdx.x);
+    zero_pads(y2 + (int64_t)row * slab, L, K, blockIdx.x);
   }
 }
 
 // out = M z1 + A z2, plus M e_b in row 0 of right-hand side b
 template <typename T>
-__global__ __launch_bounds__(kBlock3) void combine3_kernel(const T* __restrict__ z1,
-                                                          const T* __restrict__ z2,
-                                                          const T* __restrict__ extra,
-                                                          int64_t extra_stride, T* __restrict__ out,
-                                                          int J, int K, int rows) {
+__global__ __launch_bounds__(kLane) void combine3_kernel(const T* __restrict__ z1,
+                                                        const T* __restrict__ z2,
+                                                        const T* __restrict__ extra,
+                                                        int64_t extra_stride, T* __restrict__ out,
+                                                        int J, int K, int rows) {
   const int N = 1 << J;
   const int64_t slab = slab3_elems(K);
   const C3 ca = coef3(1.0, 0.0, K), cm = coef3(0.0, 1.0, K);
-  FOR_ELEMS_3D(K, rows) {
-    Node3 p;
-    T v = T(0);
-    if (node3_of(idx, K, p)) {
-      v = stencil3(z1 + row * slab, K, p, cm, 0, 15) + stencil3(z2 + row * slab, K, p, ca, 0, 7);
-      const int rhs = row / (N + 1), i = row - rhs * (N + 1);
-      if (i == 0 && extra) v += stencil3(extra + (int64_t)rhs * extra_stride, K, p, cm, 0, 15);
+  FOR_LINE_ROWS(K, rows) {
+    const int rhs = row / (N + 1), ti = row - rhs * (N + 1);
+    const T* a1 = z1 + (int64_t)row * slab;
+    const T* a2 = z2 + (int64_t)row * slab;
+    const T* e = (ti == 0 && extra) ? extra + (int64_t)rhs * extra_stride : nullptr;
+    T* o = out + (int64_t)row * slab;
+    for (int i = 1 + threadIdx.x; i <= L.n; i += kLane) {
+      T v = mass3(a1, L, i, cm) + (T(ca.c0) * nb3<T, 0, 0, 0>(a2, L, i) + off3<T, false>(a2, L, i, ca));
+      if (e) v += mass3(e, L, i, cm);
+      o[L.off + i - 1] = v;
     }
-    out[row * slab + idx] = v;
+    zero_pads(o, L, K, blockIdx.x);
   }
 }
 
-// One colour of Gauss-Seidel on level l for C = a A + sigma_row M.
-template <typename T>
-__global__ __launch_bounds__(kBlock3) void relax3_kernel(T* __restrict__ x,
-                                                         const T* __restrict__ b, int l, int rows,
-                                                         double a,
-                                                         const double* __restrict__ sigma,
-                                                         int colour) {
-  FOR_ELEMS_3D(l, rows) {
-    Node3 p;
-    if (!node3_of(idx, l, p) || ((p.i + p.j + p.k) & 3) != colour) continue;
+// One colour of Gauss-Seidel on level l for C = a A + sigma_row M: lanes
+// take the nodes of the line with (i + j + k) mod 4 == colour.
+template <typename T, bool DIAG>
+__global__ __launch_bounds__(kLane) void relax3_kernel(T* __restrict__ x,
+                                                       const T* __restrict__ b, int l, int rows,
+                                                       double a, const double* __restrict__ sigma,
+                                                       int colour) {
+  FOR_LINE_ROWS(l, rows) {
     const C3 c = coef3(a, sigma ? sigma[row] : 0.0, l);
+    const T inv = T(1.0 / c.c0);
     T* xr = x + row * slab3_elems(l);
-    const T off = stencil3(xr, l, p, c, 1, sigma ? 15 : 7);
-    xr[idx] = (b[row * slab3_elems(l) + idx] - off) / T(c.w[0]);
+    const T* br = b + row * slab3_elems(l);
+    int i0 = ((colour - L.j - L.k) % 4 + 4) % 4;
+    if (i0 == 0) i0 = 4;
+    for (int i = i0 + 4 * threadIdx.x; i <= L.n; i += 4 * kLane)
+      xr[L.off + i - 1] = (br[L.off + i - 1] - off3<T, DIAG>(xr, L, i, c)) * inv;
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock3) void residual3_kernel(const T* __restrict__ x,
-                                                            const T* __restrict__ b,
-                                                            T* __restrict__ r, int l, int rows,
-                                                            double a,
-                                                            const double* __restrict__ sigma) {
-  FOR_ELEMS_3D(l, rows) {
-    Node3 p;
-    T v = T(0);
-    if (node3_of(idx, l, p)) {
-      const C3 c = coef3(a, sigma ? sigma[row] : 0.0, l);
-      v = b[row * slab3_elems(l) + idx] -
-          stencil3(x + row * slab3_elems(l), l, p, c, 0, sigma ? 15 : 7);
-    }
-    r[row * slab3_elems(l) + idx] = v;
+template <typename T, bool DIAG>
+__global__ __launch_bounds__(kLane) void residual3_kernel(const T* __restrict__ x,
+                                                          const T* __restrict__ b,
+                                                          T* __restrict__ r, int l, int rows,
+                                                          double a,
+                                                          const double* __restrict__ sigma) {
+  FOR_LINE_ROWS(l, rows) {
+    const C3 c = coef3(a, sigma ? sigma[row] : 0.0, l);
+    const T* xr = x + row * slab3_elems(l);
+    const T* br = b + row * slab3_elems(l);
+    T* rr = r + row * slab3_elems(l);
+    for (int i = 1 + threadIdx.x; i <= L.n; i += kLane)
+      rr[L.off + i - 1] = br[L.off + i - 1] - (T(c.c0) * nb3<T, 0, 0, 0>(xr, L, i) +
+                                                off3<T, DIAG>(xr, L, i, c));
   }
 }
 
 // bc (level l - 1) = P^T r (level l): the coarse node's own fine value plus
-// half of each of its 14 fine neighbours along the edge directions.
+// half of each of its 14 fine neighbours along the edge directions.  The
+// wave runs over a coarse line; Lf addresses the fine line through 2J, 2K.
 template <typename T>
-__global__ __launch_bounds__(kBlock3) void restrict3_kernel(const T* __restrict__ r,
-                                                            T* __restrict__ bc, int l, int rows) {
+__global__ __launch_bounds__(kLane) void restrict3_kernel(const T* __restrict__ r,
+                                                          T* __restrict__ bc, int l, int rows) {
   const int lc = l - 1;
-  FOR_ELEMS_3D(lc, rows) {
-    Node3 p;
-    T v = T(0);
-    if (node3_of(idx, lc, p)) {
-      const T* rr = r + row * slab3_elems(l);
-      const int i = 2 * p.i, j = 2 * p.j, k = 2 * p.k;
-      T half = T(0);
-      for (int q = 1; q < 15; ++q) half += at3(rr, l, i + kOff[q][0], j + kOff[q][1], k + kOff[q][2]);
-      v = at3(rr, l, i, j, k) + T(0.5) * half;
+  FOR_LINE_ROWS(lc, rows) {
+    Line3 Lf;
+    Lf.n = grid_n(l);
+    Lf.pitch = line_pitch(l);
+    Lf.j = 2 * L.j;
+    Lf.k = 2 * L.k;
+    Lf.off = ((int64_t)(Lf.k - 1) * Lf.n + (Lf.j - 1)) * Lf.pitch;
+    const T* rr = r + row * slab3_elems(l);
+    T* o = bc + row * slab3_elems(lc);
+    for (int I = 1 + threadIdx.x; I <= L.n; I += kLane) {
+      const int i = 2 * I;
+      const T half = (axis_sum(rr, Lf, i) + face_sum(rr, Lf, i)) + body_sum(rr, Lf, i);
+      o[L.off + I - 1] = nb3<T, 0, 0, 0>(rr, Lf, i) + T(0.5) * half;
     }
-    bc[row * slab3_elems(lc) + idx] = v;
+    zero_pads(o, L, lc, blockIdx.x);
   }
 }
 
 // x (level l) += P e (e on level l - 1): fine node (2I + a, 2J + b, 2K + c)
 // takes the mean of the coarse ends of the edge it bisects.
 template <typename T>
-__global__ __launch_bounds__(kBlock3) void prolong_add3_kernel(const T* __restrict__ e,
-                                                               T* __restrict__ x, int l, int rows) {
-  FOR_ELEMS_3D(l, rows) {
-    Node3 p;
-    if (!node3_of(idx, l, p)) continue;
+__global__ __launch_bounds__(kLane) void prolong_add3_kernel(const T* __restrict__ e,
+                                                             T* __restrict__ x, int l, int rows) {
+  FOR_LINE_ROWS(l, rows) {
+    const int nc = grid_n(l - 1), pc = line_pitch(l - 1);
     const T* ee = e + row * slab3_elems(l - 1);
-    const int a = p.i & 1, b = p.j & 1, c = p.k & 1;
-    const int I = p.i >> 1, J = p.j >> 1, Kc = p.k >> 1;
-    T v = at3(ee, l - 1, I, J, Kc);
-    if (a | b | c) v = T(0.5) * (v + at3(ee, l - 1, I + a, J + b, Kc + c));
-    x[row * slab3_elems(l) + idx] += v;
+    T* xr = x + row * slab3_elems(l);
+    const int bb = L.j & 1, cc = L.k & 1, J = L.j >> 1, Kc = L.k >> 1;
+    auto at = [&](int I, int Jn, int Kn) -> T {
+      return (I >= 1 && I <= nc && Jn >= 1 && Jn <= nc && Kn >= 1 && Kn <= nc)
+                 ? ee[((int64_t)(Kn - 1) * nc + (Jn - 1)) * pc + (I - 1)]
+                 : T(0);
+    };
+    for (int i = 1 + threadIdx.x; i <= L.n; i += kLane) {
+      const int aa = i & 1, I = i >> 1;
+      T v = at(I, J, Kc);
+      if (aa | bb | cc) v = T(0.5) * (v + at(I + aa, J + bb, Kc + cc));
+      xr[L.off + i - 1] += v;
+    }
   }
 }
 
@@ -303,12 +360,12 @@ __global__ void coarsest3_kernel(const T* __restrict__ b, T* __restrict__ x, int
   if (row >= rows) return;
   const C3 c = coef3(a, sigma ? sigma[row] : 0.0, 1);
   const int64_t s = slab3_elems(1);
-  x[row * s] = b[row * s] / T(c.w[0]);
+  x[row * s] = b[row * s] / T(c.c0);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock3) void zero3_kernel(T* __restrict__ x, int64_t count) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock3 + threadIdx.x;
+__global__ __launch_bounds__(256) void zero3_kernel(T* __restrict__ x, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < count) x[i] = T(0);
 }
 
@@ -316,41 +373,41 @@ __global__ __launch_bounds__(kBlock3) void zero3_kernel(T* __restrict__ x, int64
 
 template <typename T>
 hipError_t pack3(hipStream_t s, const double* src, T* dst, int K, int rows) {
-  pack3_kernel<T><<<grid3(K, rows), kBlock3, 0, s>>>(src, dst, K, rows);
+  pack3_kernel<T><<<grid3(K, rows), kLane, 0, s>>>(src, dst, K, rows);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t unpack3(hipStream_t s, const T* src, double* dst, int K, int rows) {
-  unpack3_kernel<T><<<grid3(K, rows), kBlock3, 0, s>>>(src, dst, K, rows);
+  unpack3_kernel<T><<<grid3(K, rows), kLane, 0, s>>>(src, dst, K, rows);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t apply_A3(hipStream_t s, const T* x, T* y, int K, int rows) {
-  apply3_kernel<T><<<grid3(K, rows), kBlock3, 0, s>>>(x, y, K, rows, 1.0, 0.0);
+  apply3_kernel<T><<<grid3(K, rows), kLane, 0, s>>>(x, y, K, rows, 1.0, 0.0);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t apply_M3(hipStream_t s, const T* x, T* y, int K, int rows) {
-  apply3_kernel<T><<<grid3(K, rows), kBlock3, 0, s>>>(x, y, K, rows, 0.0, 1.0);
+  apply3_kernel<T><<<grid3(K, rows), kLane, 0, s>>>(x, y, K, rows, 0.0, 1.0);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t time_stencil_pair3(hipStream_t s, const T* X, T* y1, T* y2, int J, int K, int nrhs) {
   const int rows = nrhs * ((1 << J) + 1);
-  time_pair3_kernel<T, 0><<<grid3(K, rows), kBlock3, 0, s>>>(X, y1, y2, J, K, rows);
+  time_pair3_kernel<T, 0><<<grid3(K, rows), kLane, 0, s>>>(X, y1, y2, J, K, rows);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t rhs_stencil_pair3(hipStream_t s, const T* g, T* G1, T* G0, int J, int K, int nrhs) {
   const int rows = nrhs * ((1 << J) + 1);
-  time_pair3_kernel<T, 1><<<grid3(K, rows), kBlock3, 0, s>>>(g, G1, G0, J, K, rows);
+  time_pair3_kernel<T, 1><<<grid3(K, rows), kLane, 0, s>>>(g, G1, G0, J, K, rows);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t combine3(hipStream_t s, const T* z1, const T* z2, const T* extra, int64_t extra_stride,
                     T* out, int J, int K, int nrhs) {
   const int rows = nrhs * ((1 << J) + 1);
-  combine3_kernel<T><<<grid3(K, rows), kBlock3, 0, s>>>(z1, z2, extra, extra_stride, out, J, K,
+  combine3_kernel<T><<<grid3(K, rows), kLane, 0, s>>>(z1, z2, extra, extra_stride, out, J, K,
                                                         rows);
   return hipGetLastError();
 }
@@ -360,21 +417,30 @@ template <typename T>
 hipError_t vcycle3(hipStream_t s, const Mg3Work<T>& w, T* x, const T* b, int l, int rows,
                    double a, const double* sigma) {
   const dim3 g = grid3(l, rows);
+  auto relax = [&](int c) {
+    if (sigma)
+      relax3_kernel<T, true><<<g, kLane, 0, s>>>(x, b, l, rows, a, sigma, c);
+    else
+      relax3_kernel<T, false><<<g, kLane, 0, s>>>(x, b, l, rows, a, sigma, c);
+  };
   for (int sw = 0; sw < 3; ++sw)
-    for (int c = 0; c < 4; ++c) relax3_kernel<T><<<g, kBlock3, 0, s>>>(x, b, l, rows, a, sigma, c);
-  residual3_kernel<T><<<g, kBlock3, 0, s>>>(x, b, w.r[l], l, rows, a, sigma);
-  restrict3_kernel<T><<<grid3(l - 1, rows), kBlock3, 0, s>>>(w.r[l], w.b[l - 1], l, rows);
+    for (int c = 0; c < 4; ++c) relax(c);
+  if (sigma)
+    residual3_kernel<T, true><<<g, kLane, 0, s>>>(x, b, w.r[l], l, rows, a, sigma);
+  else
+    residual3_kernel<T, false><<<g, kLane, 0, s>>>(x, b, w.r[l], l, rows, a, sigma);
+  restrict3_kernel<T><<<grid3(l - 1, rows), kLane, 0, s>>>(w.r[l], w.b[l - 1], l, rows);
   if (l - 1 == 1) {
     coarsest3_kernel<T><<<(rows + 63) / 64, 64, 0, s>>>(w.b[1], w.x[1], rows, a, sigma);
   } else {
     const int64_t cnt = (int64_t)rows * slab3_elems(l - 1);
-    zero3_kernel<T><<<(unsigned)((cnt + kBlock3 - 1) / kBlock3), kBlock3, 0, s>>>(w.x[l - 1], cnt);
+    zero3_kernel<T><<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(w.x[l - 1], cnt);
     const hipError_t e = vcycle3<T>(s, w, w.x[l - 1], w.b[l - 1], l - 1, rows, a, sigma);
     if (e != hipSuccess) return e;
   }
-  prolong_add3_kernel<T><<<g, kBlock3, 0, s>>>(w.x[l - 1], x, l, rows);
+  prolong_add3_kernel<T><<<g, kLane, 0, s>>>(w.x[l - 1], x, l, rows);
   for (int sw = 0; sw < 3; ++sw)
-    for (int c = 3; c >= 0; --c) relax3_kernel<T><<<g, kBlock3, 0, s>>>(x, b, l, rows, a, sigma, c);
+    for (int c = 3; c >= 0; --c) relax(c);
   return hipGetLastError();
 }
 
@@ -383,7 +449,7 @@ hipError_t mg3_apply(hipStream_t s, const Mg3Work<T>& w, const T* b, T* x, int K
                      double a, const double* sigma, int vcycles, bool write_Ax) {
   T* xk = write_Ax ? w.x[K] : x;
   const int64_t cnt = (int64_t)rows * slab3_elems(K);
-  zero3_kernel<T><<<(unsigned)((cnt + kBlock3 - 1) / kBlock3), kBlock3, 0, s>>>(xk, cnt);
+  zero3_kernel<T><<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(xk, cnt);
   if (K == 1) {
     coarsest3_kernel<T><<<(rows + 63) / 64, 64, 0, s>>>(b, xk, rows, a, sigma);
   } else {
