@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 import synth
+from oracle import space3d
 from oracle.schur import Problem
 from tests.gpu_helpers import rel_err
 
@@ -62,6 +63,36 @@ def test_operators_3d(stp, J, K, prec):
             err = _max_rel(out.reshape(P.shape), _oracle_op(P, name, X))
             say(f"3D J={J} K={K} {prec} {name}: {err:.2e}")
             assert err <= (1e-12 if prec == "FP64" else 2e-4), name
+    finally:
+        stp.stp_destroy(ctx)
+
+
+@pytest.mark.parametrize("J,K,names", [(1, 6, ["S", "KX", "SHAT", "W", "WT"]),
+                                        (0, 7, ["A", "M", "KSPACE"])])
+@pytest.mark.parametrize("prec", ["FP64", "MIXED"])
+def test_operators_3d_long_lines(stp, J, K, names, prec):
+    """Grid lines of 63 and 127 nodes: a full wave, and two passes of one,
+    per line in every spatial kernel; 7 multigrid levels."""
+    P = Problem(J, K, dim=3)
+    X = synth.random_field(P.shape, 900 + K)
+    p = getattr(stp, "STP_" + prec)
+    ctx = stp.stp_create(J, K, 1, p, D3)
+    try:
+        for name in names:
+            out = np.zeros(X.size)
+            stp.stp_apply(ctx, getattr(stp, "STP_OP_" + name), p, 0, flat(X), out)
+            err = _max_rel(out.reshape(P.shape), _oracle_op(P, name, X))
+            tol = 1e-12 if prec == "FP64" else 2e-4
+            if name == "KX":
+                # the rounding of y = K_l r grows by the cancellation in A y
+                # (12 = the sum of the stiffness weights' magnitudes over h)
+                lev = oracle.wavelet.row_levels(J)
+                y = space3d.mg_apply(X, K, P.alpha, 2.0 ** lev.astype(np.float64), P.cycles, P.sweeps)
+                amp = 12.0 * np.abs(y).max() / np.abs(P.A(y)).max()
+                eps = np.finfo(np.float64 if prec == "FP64" else np.float32).eps / 2
+                tol = max(tol, 500 * eps * amp)
+            say(f"3D J={J} K={K} {prec} {name}: {err:.2e} (bound {tol:.1e})")
+            assert err <= tol, name
     finally:
         stp.stp_destroy(ctx)
 
