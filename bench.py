@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--workload", default="heat2d_J12_K9", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--lookahead", type=int, default=0, choices=[0, -1],
+                    help="0: PCG iterations in batches between flag reads; -1: read after each")
     ap.add_argument("--no-compare", action="store_true", help="skip the other-precision run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-seconds", type=float, default=20.0)
@@ -326,7 +328,7 @@ def run_serving(args, stp, torch):
     cal = reqs if args.calibration_requests <= 0 else synth.serving_stream(
         args.calibration_requests, seed=12344)
     server = stp.stp_server_create(int(args.budget_gb * 1e9), max_slots=args.slots,
-                                   max_batch=args.batch)
+                                   max_batch=args.batch, options={"lookahead": args.lookahead})
     try:
         serve_stream(stp, torch, server, warm, prec, None)  # code loading, allocator warm-up
         res_cal, span_cal = serve_stream(stp, torch, server, cal, prec, None)
@@ -382,7 +384,8 @@ def run_serving(args, stp, torch):
         "config": {"workload": "heat2d_serve", "requests": len(res), "unknowns_total": unknowns,
                    "J": "6..11", "K": "5..9", "rel_tol": "1e-10..1e-6", "precision": args.precision,
                    "load": args.load, "slots": args.slots, "batch": args.batch,
-                   "budget_gb": args.budget_gb, "parallelism": "single-gpu"},
+                   "budget_gb": args.budget_gb, "lookahead": args.lookahead,
+                   "parallelism": "single-gpu"},
         "roofline": None,
         "cpu_baseline": None,
         "serving": serving,
@@ -406,7 +409,7 @@ def main():
     J, K, nrhs, seed, u0kind = WORKLOADS[args.workload]
     prec = stp.STP_FP64 if args.precision == "fp64" else stp.STP_MIXED
     dim = 3 if u0kind == "sin3" else 2
-    opts = {"dim": 3} if dim == 3 else None
+    opts = {"dim": dim, "lookahead": args.lookahead}
     unknowns = (2 ** J + 1) * (2 ** K - 1) ** dim * nrhs
     print(f"# workload {args.workload} J={J} K={K} nrhs={nrhs} precision={args.precision}",
           file=sys.stderr, flush=True)

@@ -92,6 +92,14 @@ typedef struct {
                            ((c - 1)(2^K - 1) + (b - 1))(2^K - 1) + (a - 1); the heat
                            equation only (no nesting, diffusion or reaction), not for
                            the server; stp_footprint counts two dimensions */
+  int lookahead;        /* when the host reads the per-right-hand-side convergence
+                           flags (Section 3.4's stopping test is taken on the device):
+                           0 (default) -> after a batch of PCG iterations of half the
+                           remaining count that the observed mean reduction of
+                           sqrt(r^T z) per iteration predicts (all remaining ones
+                           with rel_tol = 0); -1 -> after every iteration.  Iterations
+                           past a right-hand side's stop change nothing of it, so
+                           results and iteration counts do not depend on this */
 } stp_options;
 
 typedef struct {

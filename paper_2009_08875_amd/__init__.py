@@ -37,7 +37,7 @@ class stp_options(ctypes.Structure):
                 ("maxit", ctypes.c_int), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int),
                 ("graph", ctypes.c_int), ("nested", ctypes.c_int),
                 ("diffusion", ctypes.c_double * 3), ("reaction", ctypes.c_double),
-                ("dim", ctypes.c_int)]
+                ("dim", ctypes.c_int), ("lookahead", ctypes.c_int)]
 
 
 class stp_stats(ctypes.Structure):

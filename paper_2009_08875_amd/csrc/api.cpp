@@ -46,6 +46,7 @@ stp_options resolve(const stp_options* o) {
   if (r.max_outer <= 0) r.max_outer = 20;
   if (r.graph > 0) r.graph = 1;
   if (r.nested < 0) r.nested = 0;
+  r.lookahead = r.lookahead < 0 ? -1 : 0;
   if (r.diffusion[0] == 0.0 && r.diffusion[1] == 0.0 && r.diffusion[2] == 0.0) {
     r.diffusion[0] = 1.0;
     r.diffusion[1] = 1.0;
@@ -163,6 +164,7 @@ stp_status plan_context(Arena& ar, stp_ctx* c) {
   STP_TRY(ar.get(&c->sc.active, c->nrhs));
   STP_TRY(ar.get(&c->sc.its, c->nrhs));
   STP_TRY(ar.get(&c->sc.status, c->nrhs));
+  STP_TRY(ar.get(&c->dflags, 5 * (int64_t)c->nrhs));
   STP_TRY(plan_ops(ar, c->ops64, c->K, c->rows, vec, c->dim));
   if (c->prec == STP_FP64) {
     STP_TRY(plan_pcg(ar, c->pcg64, vec, false));
@@ -532,22 +534,54 @@ stp_status iterate(stp_ctx* c, PcgVecs<T>& v) {
   return STP_OK;
 }
 
-// Copy the lane flags to pinned host memory and mark the end of the unit.
+// Copy the convergence state to pinned host memory and mark the end of the
+// unit.
 stp_status post_flags(stp_ctx* c) {
   const int nr = c->nrhs;
-  HIP_TRY(hipMemcpyAsync(c->h_flags, c->sc.active, sizeof(int) * nr, hipMemcpyDeviceToHost,
+  HIP_TRY(pack_flags(c->stream, c->sc, nr, c->dflags));
+  HIP_TRY(hipMemcpyAsync(c->h_flags, c->dflags, sizeof(double) * 5 * nr, hipMemcpyDeviceToHost,
                          c->stream));
-  if (c->prec == STP_MIXED)
-    HIP_TRY(hipMemcpyAsync(c->h_flags + nr, c->ms.done, sizeof(int) * nr, hipMemcpyDeviceToHost,
-                           c->stream));
   HIP_TRY(hipEventRecord(c->ev_flags, c->stream));
   return STP_OK;
 }
 
 bool any_active(const stp_ctx* c) {
   for (int b = 0; b < c->nrhs; ++b)
-    if (c->h_flags[b]) return true;
+    if (c->h_flags[5 * b] != 0.0) return true;
   return false;
+}
+
+// How many PCG iterations to enqueue before the host reads the flags again.
+// Per active right-hand side: with target 0 (run to the limit) all that are
+// left; else half of log(sqrt(rho) / target) / -log(q) with q the mean
+// reduction of sqrt(rho) per iteration so far, and 1 before the first
+// iteration.  The batch is the largest over the active right-hand sides: an
+// iteration enqueued after every one has stopped is wasted time, never a
+// change of results (inactive right-hand sides get gamma = 0).
+int iteration_batch(const stp_ctx* c) {
+  if (c->opt.lookahead < 0) return 1;
+  const double* h = c->h_flags;
+  const int maxit = c->opt.maxit;
+  int batch = 1;
+  for (int b = 0; b < c->nrhs; ++b) {
+    if (h[5 * b] == 0.0) continue;
+    const int its = (int)h[5 * b + 1];
+    const double rho = h[5 * b + 2], rho0 = h[5 * b + 3], target = h[5 * b + 4];
+    const int left = maxit - its;
+    int m = 1;
+    if (target <= 0.0) {
+      m = left;
+    } else if (its > 0 && rho > 0.0 && rho0 > 0.0) {
+      const double d = std::sqrt(rho) / target;
+      const double q = std::pow(rho / rho0, 0.5 / its);
+      if (q > 0.0 && q < 1.0 && d > 1.0) {
+        const double est = 0.5 * std::log(d) / -std::log(q);
+        m = est >= (double)left ? left : std::max(1, (int)est);
+      }
+    }
+    batch = std::max(batch, std::min(m, left));
+  }
+  return std::max(batch, 1);
 }
 
 // Last unit: u = W w (out of place), and the statistics to pinned host memory.
@@ -692,10 +726,13 @@ stp_status drive_next(stp_ctx* c) {
     return STP_E_INVALID_ARG;
   }
   if (any_active(c)) {
-    if (c->prec == STP_FP64)
-      STP_TRY(iterate<double>(c, c->pcg64));
-    else
-      STP_TRY(iterate<float>(c, c->pcg32));
+    const int m = iteration_batch(c);
+    for (int i = 0; i < m; ++i) {
+      if (c->prec == STP_FP64)
+        STP_TRY(iterate<double>(c, c->pcg64));
+      else
+        STP_TRY(iterate<float>(c, c->pcg32));
+    }
     d.adjusted = false;
     return post_flags(c);
   }
@@ -908,7 +945,7 @@ stp_status stp_create(int J, int K, int nrhs, int precision, const stp_options* 
   stp_status st = plan_context(ar, c);
   if (st < 0) return fail(st);
   c->bytes = ar.bytes;
-  if (hipHostMalloc((void**)&c->h_flags, sizeof(int) * 2 * nrhs) != hipSuccess ||
+  if (hipHostMalloc((void**)&c->h_flags, sizeof(double) * 5 * nrhs) != hipSuccess ||
       hipHostMalloc((void**)&c->h_stats, sizeof(double) * 4 * nrhs) != hipSuccess ||
       hipHostMalloc((void**)&c->h_tol, sizeof(double) * nrhs) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_flags, hipEventDisableTiming) != hipSuccess ||

@@ -153,6 +153,9 @@ struct PcgScalars {
 // side, the reference of the stopping test and of rho0 from an initial guess.
 hipError_t pcg_start(hipStream_t s, PcgScalars sc, int nrhs, const double* tol,
                      const double* ref = nullptr);
+// The convergence state the host reads after a unit of work, packed per
+// right-hand side b as out[5b .. 5b+4] = active, its, rho, rho0, target.
+hipError_t pack_flags(hipStream_t s, PcgScalars sc, int nrhs, double* out);
 // gamma = rho / p^T q for active right-hand sides (breakdown if p^T q <= 0).
 hipError_t pcg_gamma(hipStream_t s, PcgScalars sc, int nrhs);
 // beta = rhonew / rho, rho = rhonew, its += 1, convergence test against target;

@@ -622,6 +622,16 @@ __global__ void pcg_start_kernel(PcgScalars sc, int nrhs, const double* __restri
   }
 }
 
+__global__ void pack_flags_kernel(PcgScalars sc, int nrhs, double* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nrhs) return;
+  out[5 * b] = (double)sc.active[b];
+  out[5 * b + 1] = (double)sc.its[b];
+  out[5 * b + 2] = sc.rho[b];
+  out[5 * b + 3] = sc.rho0[b];
+  out[5 * b + 4] = sc.target[b];
+}
+
 __global__ void pcg_gamma_kernel(PcgScalars sc, int nrhs) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nrhs) return;
@@ -1012,6 +1022,10 @@ hipError_t update_p(hipStream_t s, T* p, const T* z, const double* beta, int64_t
 
 hipError_t pcg_start(hipStream_t s, PcgScalars sc, int nrhs, const double* tol, const double* ref) {
   pcg_start_kernel<<<blocks_for(nrhs, 64), 64, 0, s>>>(sc, nrhs, tol, ref);
+  return hipGetLastError();
+}
+hipError_t pack_flags(hipStream_t s, PcgScalars sc, int nrhs, double* out) {
+  pack_flags_kernel<<<blocks_for(nrhs, 64), 64, 0, s>>>(sc, nrhs, out);
   return hipGetLastError();
 }
 hipError_t pcg_gamma(hipStream_t s, PcgScalars sc, int nrhs) {

@@ -95,7 +95,8 @@ struct stp_ctx {
   double* tolv = nullptr;    // relative tolerance per right-hand side (device)
 
   // pinned host memory read between units of a solve
-  int* h_flags = nullptr;     // active[nrhs] | done[nrhs]
+  double* h_flags = nullptr;  // pinned copy of dflags
+  double* dflags = nullptr;   // per right-hand side: active, its, rho, rho0, target
   double* h_stats = nullptr;  // 2 * nrhs doubles, then 4 * nrhs ints
   double* h_tol = nullptr;    // nrhs
   hipEvent_t ev_flags = nullptr;
