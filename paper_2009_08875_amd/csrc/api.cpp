@@ -297,13 +297,12 @@ stp_status mg_apply(stp_ctx* c, MgScratch<T>& mg, const T* b, T* x, int64_t rows
     const T* bb = b + r0 * slab;
     T* xx = x + r0 * slab;
     const double* sg = sigma ? sigma + r0 : nullptr;
-    if (K <= kCoarseLevels) {
-      // the whole cycle fits one workgroup per row (all levels in LDS)
-      for (int cyc = 0; cyc < c->opt.vcycles; ++cyc) {
-        const bool last = cyc == c->opt.vcycles - 1;
-        HIP_TRY(mg_coarse_cycle<T>(c->stream, cyc == 0 ? nullptr : xx, bb, xx, K, nr, a, sg,
-                                   write_Ax && last, c->op));
-      }
+    constexpr int CL = coarse_levels<T>();
+    if (K <= CL) {
+      // every cycle in one workgroup per row (all levels in LDS): b read
+      // once, x written once
+      HIP_TRY(mg_coarse_cycle<T>(c->stream, nullptr, bb, xx, K, nr, a, sg, write_Ax, c->op,
+                                 c->opt.vcycles));
       continue;
     }
     // algorithmic bytes of the fine-level kernels: every input element read
@@ -318,13 +317,13 @@ stp_status mg_apply(stp_ctx* c, MgScratch<T>& mg, const T* b, T* x, int64_t rows
       STP_TRY(timed_launch(c, STP_KERNEL_MG_PRE, pre_bytes, [&] {
         return mg_pre_stream<T>(c->stream, xin, bb, mg.xb[K], mg.b[K - 1], K, nr, a, sg, c->op);
       }));
-      for (int l = K - 1; l > kCoarseLevels; --l)
+      for (int l = K - 1; l > CL; --l)
         HIP_TRY(mg_pre_stream<T>(c->stream, nullptr, mg.b[l], mg.xb[l], mg.b[l - 1], l, nr, a, sg,
                                  c->op));
-      // levels kCoarseLevels .. 1 in one launch, from zero
-      HIP_TRY(mg_coarse_cycle<T>(c->stream, nullptr, mg.b[kCoarseLevels], mg.xa[kCoarseLevels],
-                                 kCoarseLevels, nr, a, sg, false, c->op));
-      for (int l = kCoarseLevels + 1; l <= K - 1; ++l)
+      // levels CL .. 1 in one launch, from zero
+      HIP_TRY(mg_coarse_cycle<T>(c->stream, nullptr, mg.b[CL], mg.xa[CL], CL, nr, a, sg, false,
+                                 c->op));
+      for (int l = CL + 1; l <= K - 1; ++l)
         HIP_TRY(mg_post_stream<T>(c->stream, mg.xb[l], mg.b[l], mg.xa[l - 1], mg.xa[l], l, nr, a, sg,
                                   false, c->op));
       const double post_bytes = sizeof(T) * (3.0 * nodes + cnodes);

@@ -61,13 +61,22 @@ hipError_t mg_post_stream(hipStream_t s, const T* xin, const T* b, const T* ec, 
                           int rows, double a, const double* sigma, bool write_Ax,
                           const SpaceOp& op);
 
-// One V-cycle on levels L..1 (L <= kCoarseLevels) per row, each row in one
-// workgroup with all levels in LDS (mg_coarse.hip): xout = V(L, b, xin) (xin
-// NULL: from zero), or A_x applied to it when write_Ax.  xout may alias xin.
-constexpr int kCoarseLevels = 5;
+// `cycles` V-cycles on levels L..1 (L <= coarse_levels<T>()) per row, each row
+// in one workgroup with all levels in LDS (mg_coarse.hip): xout =
+// V^cycles(L, b, xin) (xin NULL: from zero), or A_x applied to it when
+// write_Ax.  xout may alias xin.  Level 6 would fit LDS too (62.6 KB in FP32),
+// but one workgroup per row on 3969 nodes is slower than streaming that
+// level: at 64 right-hand sides of N = 2^8, h = 2^-7 the level-6 cycle took
+// 1.73 ms per launch against about 1.0 ms for the two level-6 streaming
+// launches and the level-5 cycle.
+template <typename T>
+constexpr int coarse_levels() {
+  return 5;
+}
 template <typename T>
 hipError_t mg_coarse_cycle(hipStream_t s, const T* xin, const T* b, T* xout, int L, int rows,
-                           double a, const double* sigma, bool write_Ax, const SpaceOp& op);
+                           double a, const double* sigma, bool write_Ax, const SpaceOp& op,
+                           int cycles = 1);
 
 // ---- space-time stencils (Lemma 4.2 and Lemma 4.1, applied row-wise through
 // the Kronecker identity, eq. (15) of Section 5.2).  X has nrhs * (2^J+1) slabs

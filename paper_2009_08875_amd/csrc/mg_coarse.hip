@@ -1,17 +1,24 @@
-// Whole V-cycles on the coarse grids, one workgroup per time row, in LDS.
+// Whole V-cycles on small grids, one workgroup per time row, in LDS.
 //
 // The streaming kernels (mg_stream.hip) need a grid wide enough to keep a
-// wavefront busy; on grids of at most 31 x 31 nodes their launches are short
-// and the cycle becomes a chain of ~20 launch latencies.  This kernel runs
-// the part of a V-cycle on levels L..1 (L <= kCoarseLevels) of one time row
-// in a single workgroup: the right-hand side is read from HBM once, every
-// level's iterate and right-hand side live in LDS, and the result (or A_x
-// applied to it) is written once.  The schedule is the one the streaming
-// kernels follow (Section 3.1, Section 5.1: three Gauss-Seidel steps in the
-// colours (i + j) mod 3 -- forward 0, 1, 2 before the coarse grid, backward
-// 2, 1, 0 after it -- the residual restricted by P^T, the coarse correction
-// prolongated by P1 interpolation on the "/" mesh, the one-node grid solved
-// exactly), so the operator is the same.
+// wavefront busy; on small grids their launches are short and the cycle
+// becomes a chain of launch latencies.  This kernel runs V-cycles on levels
+// L..1 of one time row in a single workgroup: the right-hand side is read
+// from HBM once, every level's iterate and right-hand side live in LDS, and
+// the result (or A_x applied to it) is written once, after all the cycles
+// asked for.  The schedule is the one the streaming kernels follow (Section
+// 3.1, Section 5.1: three Gauss-Seidel steps in the colours (i + j) mod 3 --
+// forward 0, 1, 2 before the coarse grid, backward 2, 1, 0 after it -- the
+// residual restricted by P^T, the coarse correction prolongated by P1
+// interpolation on the "/" mesh, the one-node grid solved exactly), so the
+// operator is the same.
+//
+// Every level is a template parameter: grid sizes, line pitches and the
+// divisions that map a thread's work item to a node are compile-time
+// constants.  Each level's arrays are stored with a one-node zero border
+// ((n + 2) x (n + 2)), so a stencil reads its neighbours without bounds
+// checks; the border is never written.  A border read returns the zero that
+// a bounds check would, so the arithmetic is the same value for value.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -20,7 +27,6 @@
 namespace stp {
 
 namespace {
-
 
 struct LevelCoef {
   double c0, cx, cy, c2;  // centre, x- and y-neighbours, the two "/" diagonal neighbours
@@ -33,180 +39,190 @@ __device__ __forceinline__ LevelCoef level_coef(double a, double sigma, int l, c
   return {st.c0, st.cx, st.cy, st.cd, 1.0 / st.c0, st.cx == st.cy};
 }
 
+// Level l: n x n interior nodes in an (n + 2) x (n + 2) array; node (i, j),
+// 1-based, at j (n + 2) + i.
+template <int l>
+struct Lv {
+  static constexpr int n = (1 << l) - 1;
+  static constexpr int p = n + 2;
+  static constexpr int size = p * p;
+  static constexpr int m = (n + 2) / 3;  // nodes of one colour per grid line, at most
+};
 
+// LDS layout for top level L: x_l then b_l for l = L..1, then the residual
+// array of level L.
+template <int L>
+struct Layout {
+  static constexpr int x(int l) {
+    int o = 0;
+    for (int k = L; k > l; --k) o += 2 * (((1 << k) + 1) * ((1 << k) + 1));
+    return o;
+  }
+  static constexpr int b(int l) { return x(l) + ((1 << l) + 1) * ((1 << l) + 1); }
+  static constexpr int r = x(0);
+  static constexpr int total = r + ((1 << L) + 1) * ((1 << L) + 1);
+};
 
-// Compact n x n arrays in LDS; node (i, j), 1-based, at (j - 1) n + (i - 1).
-template <typename T>
-__device__ __forceinline__ T at(const T* v, int n, int i, int j) {
-  return (i >= 1 && i <= n && j >= 1 && j <= n) ? v[(j - 1) * n + (i - 1)] : T(0);
-}
-
-// sum_nb C_nb x_nb at node (i, j) (the off-centre part of the stencil)
-template <typename T>
-__device__ __forceinline__ T off_centre(const T* x, int n, int i, int j, const LevelCoef& cf) {
-  const T diag = T(cf.c2) * (at(x, n, i + 1, j + 1) + at(x, n, i - 1, j - 1));
-  if (cf.iso)
-    return T(cf.cx) * (((at(x, n, i + 1, j) + at(x, n, i - 1, j)) + at(x, n, i, j + 1)) +
-                       at(x, n, i, j - 1)) +
-           diag;
-  return (T(cf.cx) * (at(x, n, i + 1, j) + at(x, n, i - 1, j)) +
-          T(cf.cy) * (at(x, n, i, j + 1) + at(x, n, i, j - 1))) +
-         diag;
+// sum_nb C_nb x_nb at the node at offset q (the off-centre part of the stencil)
+template <int l, typename T>
+__device__ __forceinline__ T off_centre(const T* x, int q, const LevelCoef& cf) {
+  constexpr int p = Lv<l>::p;
+  const T diag = T(cf.c2) * (x[q + p + 1] + x[q - p - 1]);
+  if (cf.iso) return T(cf.cx) * (((x[q + 1] + x[q - 1]) + x[q + p]) + x[q - p]) + diag;
+  return (T(cf.cx) * (x[q + 1] + x[q - 1]) + T(cf.cy) * (x[q + p] + x[q - p])) + diag;
 }
 
 // One colour of Gauss-Seidel: every node (i, j) with (i + j) mod 3 == colour
 // gets (b - sum_nb C_nb x_nb) / C_centre from the current neighbours (no two
 // nodes of one colour are coupled, so the update is in place).
-template <int NT, typename T>
-__device__ void relax(T* x, const T* b, int n, int colour, const LevelCoef& cf) {
-  const int m = (n + 2) / 3;  // nodes of one colour per grid line, at most
+template <int l, int NT, typename T>
+__device__ __forceinline__ void relax(T* x, const T* b, int colour, const LevelCoef& cf) {
+  constexpr int n = Lv<l>::n, m = Lv<l>::m, p = Lv<l>::p;
   for (int k = threadIdx.x; k < n * m; k += NT) {
     const int j = k / m + 1;
-    int i = ((colour - j) % 3 + 3) % 3;
+    int i = (colour + 3 * n - j) % 3;
     if (i == 0) i = 3;
     i += 3 * (k % m);
     if (i > n) continue;
-    const T off = off_centre(x, n, i, j, cf);
-    x[(j - 1) * n + (i - 1)] = (b[(j - 1) * n + (i - 1)] - off) * T(cf.inv_c0);
+    const int q = j * p + i;
+    x[q] = (b[q] - off_centre<l>(x, q, cf)) * T(cf.inv_c0);
   }
 }
 
-template <int NT, typename T>
-__device__ void sweeps(T* x, const T* b, int n, const LevelCoef& cf, bool forward) {
+template <int l, int NT, typename T>
+__device__ void sweeps(T* x, const T* b, const LevelCoef& cf, bool forward) {
   for (int s = 0; s < 3; ++s) {
     for (int c = 0; c < 3; ++c) {
-      relax<NT>(x, b, n, forward ? c : 2 - c, cf);
+      relax<l, NT>(x, b, forward ? c : 2 - c, cf);
       __syncthreads();
     }
   }
 }
 
-// NT threads per workgroup (one time row each); the result does not depend on NT.
-template <typename T, int NT>
+// Down the V-cycle from level l: smooth, residual, P^T into level l - 1,
+// the cycle below, then P1 interpolation of its correction and backward
+// smoothing.  x_l holds the start iterate (zero below the top level).
+template <int L, int l, int NT, typename T>
+__device__ void vcycle(T* sh, double a, double sg, const SpaceOp& op) {
+  T* x = sh + Layout<L>::x(l);
+  T* bl = sh + Layout<L>::b(l);
+  if constexpr (l == 1) {
+    if (threadIdx.x == 0) x[Lv<1>::p + 1] = bl[Lv<1>::p + 1] * T(level_coef(a, sg, 1, op).inv_c0);
+    __syncthreads();
+  } else {
+    constexpr int n = Lv<l>::n, p = Lv<l>::p;
+    constexpr int nc = Lv<l - 1>::n, pc = Lv<l - 1>::p;
+    {
+      // the level's coefficients are formed again after the coarse cycle
+      // rather than held in registers across it
+      const LevelCoef cf = level_coef(a, sg, l, op);
+      sweeps<l, NT>(x, bl, cf, true);
+      T* r = sh + Layout<L>::r;
+      for (int k = threadIdx.x; k < n * n; k += NT) {
+        const int q = (k / n + 1) * p + k % n + 1;
+        r[q] = bl[q] - (T(cf.c0) * x[q] + off_centre<l>(x, q, cf));
+      }
+    }
+    __syncthreads();
+    const T* r = sh + Layout<L>::r;
+    T* bc = sh + Layout<L>::b(l - 1);
+    T* xc = sh + Layout<L>::x(l - 1);
+    for (int k = threadIdx.x; k < nc * nc; k += NT) {
+      const int I = k % nc + 1, J = k / nc + 1;
+      const int q = 2 * J * p + 2 * I;
+      const T half = ((((r[q + 1] + r[q - 1]) + r[q + p]) + r[q - p]) + r[q + p + 1]) + r[q - p - 1];
+      bc[J * pc + I] = r[q] + T(0.5) * half;
+      xc[J * pc + I] = T(0);
+    }
+    __syncthreads();
+    vcycle<L, l - 1, NT>(sh, a, sg, op);
+    const T* e = xc;
+    for (int k = threadIdx.x; k < n * n; k += NT) {
+      const int i = k % n + 1, j = k / n + 1;
+      const int qc = (j >> 1) * pc + (i >> 1);  // coarse node (i/2, j/2), rounded down
+      T v;
+      if (!(i & 1) && !(j & 1))
+        v = e[qc];
+      else if ((i & 1) && !(j & 1))
+        v = T(0.5) * (e[qc] + e[qc + 1]);
+      else if (!(i & 1) && (j & 1))
+        v = T(0.5) * (e[qc] + e[qc + pc]);
+      else
+        v = T(0.5) * (e[qc] + e[qc + pc + 1]);
+      x[j * p + i] += v;
+    }
+    __syncthreads();
+    sweeps<l, NT>(x, bl, level_coef(a, sg, l, op), false);
+  }
+}
+
+// `cycles` V-cycles on levels L..1 of one time row per workgroup: from xin
+// (NULL: zero), the result or A_x applied to it to xout.
+template <typename T, int NT, int L>
 __global__ __launch_bounds__(NT) void mg_coarse_kernel(const T* xin, const T* b, T* xout,
-                                                             int L, double a,
-                                                             const double* __restrict__ sigma,
-                                                             int write_Ax, SpaceOp op) {
-  extern __shared__ unsigned char smem[];
-  T* sh = reinterpret_cast<T*>(smem);
-  // LDS: x_l and b_l for l = L..1, then a residual array of level L
-  auto nl = [](int l) { return (1 << l) - 1; };
-  auto off_x = [&](int l) {
-    int o = 0;
-    for (int k = L; k > l; --k) o += 2 * nl(k) * nl(k);
-    return o;
-  };
-  auto off_b = [&](int l) { return off_x(l) + nl(l) * nl(l); };
-  T* r = sh + off_x(0);
+                                                       double a, const double* __restrict__ sigma,
+                                                       int write_Ax, SpaceOp op, int cycles) {
+  __shared__ T sh[Layout<L>::total];
+  constexpr int n = Lv<L>::n, p = Lv<L>::p, pitch = 1 << L;
+  for (int k = threadIdx.x; k < Layout<L>::total; k += NT) sh[k] = T(0);
+  __syncthreads();
   const int row = blockIdx.x;
   const double sg = sigma ? sigma[row] : 0.0;
-  const int n = nl(L), pitch = line_pitch(L);
   const int64_t base = (int64_t)row * slab_elems(L);
+  T* x = sh + Layout<L>::x(L);
+  T* bl = sh + Layout<L>::b(L);
   for (int k = threadIdx.x; k < n * n; k += NT) {
     const int64_t g = base + (int64_t)(k / n) * pitch + (k % n);
-    sh[off_b(L) + k] = b[g];
-    sh[off_x(L) + k] = xin ? xin[g] : T(0);
+    const int q = (k / n + 1) * p + k % n + 1;
+    bl[q] = b[g];
+    if (xin) x[q] = xin[g];
   }
   __syncthreads();
-  // down: smooth, residual, restrict
-  for (int l = L; l >= 2; --l) {
-    const LevelCoef cf = level_coef(a, sg, l, op);
-    T* x = sh + off_x(l);
-    const T* bl = sh + off_b(l);
-    const int nn = nl(l);
-    if (l < L) {
-      for (int k = threadIdx.x; k < nn * nn; k += NT) x[k] = T(0);
-      __syncthreads();
-    }
-    sweeps<NT>(x, bl, nn, cf, true);
-    for (int k = threadIdx.x; k < nn * nn; k += NT) {
-      const int i = k % nn + 1, j = k / nn + 1;
-      const T cx = T(cf.c0) * x[k] + off_centre(x, nn, i, j, cf);
-      r[k] = bl[k] - cx;
-    }
-    __syncthreads();
-    T* bc = sh + off_b(l - 1);
-    const int mc = nl(l - 1);
-    for (int k = threadIdx.x; k < mc * mc; k += NT) {
-      const int I = k % mc + 1, J = k / mc + 1;
-      const int i = 2 * I, j = 2 * J;
-      const T half = ((((at(r, nn, i + 1, j) + at(r, nn, i - 1, j)) + at(r, nn, i, j + 1)) +
-                       at(r, nn, i, j - 1)) +
-                      at(r, nn, i + 1, j + 1)) +
-                     at(r, nn, i - 1, j - 1);
-      bc[k] = at(r, nn, i, j) + T(0.5) * half;
-    }
-    __syncthreads();
-  }
-  // the one-node grid (h = 1/2)
-  if (threadIdx.x == 0) sh[off_x(1)] = sh[off_b(1)] * T(level_coef(a, sg, 1, op).inv_c0);
-  __syncthreads();
-  // up: prolongate the correction, smooth backwards
-  for (int l = 2; l <= L; ++l) {
-    const LevelCoef cf = level_coef(a, sg, l, op);
-    T* x = sh + off_x(l);
-    const T* e = sh + off_x(l - 1);
-    const int nn = nl(l), mc = nl(l - 1);
-    for (int k = threadIdx.x; k < nn * nn; k += NT) {
-      const int i = k % nn + 1, j = k / nn + 1;
-      T p;
-      if (!(i & 1) && !(j & 1)) {
-        p = at(e, mc, i / 2, j / 2);
-      } else if ((i & 1) && !(j & 1)) {
-        p = T(0.5) * (at(e, mc, (i - 1) / 2, j / 2) + at(e, mc, (i + 1) / 2, j / 2));
-      } else if (!(i & 1) && (j & 1)) {
-        p = T(0.5) * (at(e, mc, i / 2, (j - 1) / 2) + at(e, mc, i / 2, (j + 1) / 2));
-      } else {
-        p = T(0.5) * (at(e, mc, (i - 1) / 2, (j - 1) / 2) + at(e, mc, (i + 1) / 2, (j + 1) / 2));
-      }
-      x[k] += p;
-    }
-    __syncthreads();
-    sweeps<NT>(x, sh + off_b(l), nn, cf, false);
-  }
-  const T* x = sh + off_x(L);
+  for (int c = 0; c < cycles; ++c) vcycle<L, L, NT>(sh, a, sg, op);
   const bool heat = op.heat();
   const LevelCoef ac = level_coef(1.0, 0.0, L, op);  // A_x itself (Section 4)
   for (int k = threadIdx.x; k < n * n; k += NT) {
-    const int i = k % n + 1, j = k / n + 1;
-    T v = x[k];
+    const int q = (k / n + 1) * p + k % n + 1;
+    T v = x[q];
     if (write_Ax) {
       if (heat)
-        v = (((T(4) * v - at(x, n, i + 1, j)) - at(x, n, i - 1, j)) - at(x, n, i, j + 1)) -
-            at(x, n, i, j - 1);
+        v = (((T(4) * v - x[q + 1]) - x[q - 1]) - x[q + p]) - x[q - p];
       else
-        v = T(ac.c0) * v + off_centre(x, n, i, j, ac);
+        v = T(ac.c0) * v + off_centre<L>(x, q, ac);
     }
-    xout[base + (int64_t)(j - 1) * pitch + (i - 1)] = v;
+    xout[base + (int64_t)(k / n) * pitch + (k % n)] = v;
   }
 }
 
-size_t mg_coarse_lds_bytes(int L, size_t elem) {
-  size_t nodes = 0;
-  for (int l = L; l >= 1; --l) nodes += 2 * (size_t)((1 << l) - 1) * ((1 << l) - 1);
-  nodes += (size_t)((1 << L) - 1) * ((1 << L) - 1);
-  return nodes * elem;
+template <typename T, int NT>
+hipError_t launch_coarse(hipStream_t s, const T* xin, const T* b, T* xout, int L, int rows,
+                         double a, const double* sigma, int wa, const SpaceOp& op, int cycles) {
+  switch (L) {
+    case 1: mg_coarse_kernel<T, NT, 1><<<rows, NT, 0, s>>>(xin, b, xout, a, sigma, wa, op, cycles); break;
+    case 2: mg_coarse_kernel<T, NT, 2><<<rows, NT, 0, s>>>(xin, b, xout, a, sigma, wa, op, cycles); break;
+    case 3: mg_coarse_kernel<T, NT, 3><<<rows, NT, 0, s>>>(xin, b, xout, a, sigma, wa, op, cycles); break;
+    case 4: mg_coarse_kernel<T, NT, 4><<<rows, NT, 0, s>>>(xin, b, xout, a, sigma, wa, op, cycles); break;
+    case 5: mg_coarse_kernel<T, NT, 5><<<rows, NT, 0, s>>>(xin, b, xout, a, sigma, wa, op, cycles); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
 
 template <typename T>
 hipError_t mg_coarse_cycle(hipStream_t s, const T* xin, const T* b, T* xout, int L, int rows,
-                           double a, const double* sigma, bool write_Ax, const SpaceOp& op) {
-  if (L < 1 || L > kCoarseLevels) return hipErrorInvalidValue;
-  const size_t lds = mg_coarse_lds_bytes(L, sizeof(T));
-  // workgroups of 2, 4 or 8 waves per time row (tuned per level and row count)
+                           double a, const double* sigma, bool write_Ax, const SpaceOp& op,
+                           int cycles) {
+  if (L < 1 || L > coarse_levels<T>() || cycles < 1) return hipErrorInvalidValue;
+  const int wa = write_Ax ? 1 : 0;
+  // workgroups of 2, 4 or 8 waves per time row, tuned per level and row count
   auto go = [&](int c) -> hipError_t {
-    const int wa = write_Ax ? 1 : 0;
-    if (c == 0)
-      mg_coarse_kernel<T, 256><<<rows, 256, lds, s>>>(xin, b, xout, L, a, sigma, wa, op);
-    else if (c == 1)
-      mg_coarse_kernel<T, 128><<<rows, 128, lds, s>>>(xin, b, xout, L, a, sigma, wa, op);
-    else
-      mg_coarse_kernel<T, 512><<<rows, 512, lds, s>>>(xin, b, xout, L, a, sigma, wa, op);
-    return hipGetLastError();
+    if (c == 0) return launch_coarse<T, 256>(s, xin, b, xout, L, rows, a, sigma, wa, op, cycles);
+    if (c == 1) return launch_coarse<T, 128>(s, xin, b, xout, L, rows, a, sigma, wa, op, cycles);
+    return launch_coarse<T, 512>(s, xin, b, xout, L, rows, a, sigma, wa, op, cycles);
   };
-  const uint64_t key = tune_key(3, sizeof(T), (uint64_t)L, (uint64_t)rows);
+  const uint64_t key = tune_key(3, sizeof(T), (uint64_t)L | ((uint64_t)cycles << 8), (uint64_t)rows);
   // a cycle that starts from its own output cannot be repeated for timing:
   // it takes the choice made for the same shape from zero
   if (xin != nullptr && xin == xout) return go(tuned_choice(key, 0));
@@ -215,8 +231,8 @@ hipError_t mg_coarse_cycle(hipStream_t s, const T* xin, const T* b, T* xout, int
 
 template hipError_t mg_coarse_cycle<double>(hipStream_t, const double*, const double*, double*,
                                             int, int, double, const double*, bool,
-                                            const SpaceOp&);
+                                            const SpaceOp&, int);
 template hipError_t mg_coarse_cycle<float>(hipStream_t, const float*, const float*, float*, int,
-                                           int, double, const double*, bool, const SpaceOp&);
+                                           int, double, const double*, bool, const SpaceOp&, int);
 
 }  // namespace stp
