@@ -17,7 +17,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libstp.so")
 
 SOURCES = ["kernels.hip", "mg_stream.hip", "mg_coarse.hip", "stencil.hip", "tune.cpp", "api.cpp",
-           "server.cpp", "noalloc.hip", "space3d.hip"]
+           "server.cpp", "noalloc.hip", "space3d.hip", "wavelet_stream.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

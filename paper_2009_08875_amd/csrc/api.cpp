@@ -386,9 +386,9 @@ stp_status Shat_iteration(stp_ctx* c, Ops<T>& o, PcgVecs<T>& v) {
     return synthesis_update<T>(c->stream, v.p, v.z, c->sc.beta, o.X, c->J, c->slab, c->nrhs);
   }));
   STP_TRY(S_apply<T>(c, o, o.X, v.q, c->nrhs));
-  // q, p in; q out
+  // q (= S X), X in; q = W^T S X out, p^T q = X^T S X (X = W p)
   STP_TRY(timed_launch(c, STP_KERNEL_ANA_DOT, row_bytes<T>(c, c->rows, 3.0), [&] {
-    return analysis_dot<T>(c->stream, v.q, v.p, c->partials, c->sc.pq, c->J, c->slab, c->nrhs);
+    return analysis_dot<T>(c->stream, v.q, o.X, c->partials, c->sc.pq, c->J, c->slab, c->nrhs);
   }));
   return STP_OK;
 }

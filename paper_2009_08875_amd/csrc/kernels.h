@@ -61,6 +61,15 @@ hipError_t mg_post_stream(hipStream_t s, const T* xin, const T* b, const T* ec, 
                           int rows, double a, const double* sigma, bool write_Ax,
                           const SpaceOp& op);
 
+// The analysis W^T in one pass over the rows (wavelet_stream.hip): in place
+// on X, 0 <= J <= 14; with DOT the first pass of p^T X (X before the
+// transform), one partial per block of wavelet_stream_blocks(slab) and
+// right-hand side, to partials.
+template <typename T, bool DOT>
+hipError_t wavelet_ana_stream(hipStream_t s, T* X, const T* p, double* partials, int J,
+                              int64_t slab, int nrhs, int* nblk);
+int wavelet_stream_blocks(int64_t slab);
+
 // `cycles` V-cycles on levels L..1 (L <= coarse_levels<T>()) per row, each row
 // in one workgroup with all levels in LDS (mg_coarse.hip): xout =
 // V^cycles(L, b, xin) (xin NULL: from zero), or A_x applied to it when
@@ -116,11 +125,12 @@ hipError_t synthesis(hipStream_t s, const T* src, T* dst, int J, int64_t slab, i
 template <typename T>
 hipError_t synthesis_update(hipStream_t s, T* p, const T* z, const double* beta, T* X, int J,
                             int64_t slab, int nrhs);
-// X = W^T X in place, and out_b = p_b^T X_b (FP64, deterministic); partials
-// holds nrhs * analysis_dot_blocks(slab) values.
+// Y = W^T Y in place, and out_b = Ws_b^T Y_b with Y before the transform
+// (FP64, deterministic).  With Ws = W p this is p^T (W^T Y), the dot PCG
+// needs.  partials holds nrhs * analysis_dot_blocks(slab) values.
 int analysis_dot_blocks(int64_t slab);
 template <typename T>
-hipError_t analysis_dot(hipStream_t s, T* X, const T* p, double* partials, double* out, int J,
+hipError_t analysis_dot(hipStream_t s, T* Y, const T* Ws, double* partials, double* out, int J,
                         int64_t slab, int nrhs);
 
 // ---- vector operations over `nrhs` segments of `n` elements (segment b at

@@ -150,61 +150,6 @@ __global__ __launch_bounds__(kBlock) void wavelet_syn_kernel(const T* src, T* ds
   }
 }
 
-// Analysis W^T (fine to coarse), in place, one thread per column.  A row's
-// value is final once it is written as an odd multiple at its level (rows 0
-// and N after level 1).  With DOT each final value is multiplied by p in the
-// same row and summed per column in FP64, the columns of a block are summed
-// in a fixed order, and the block's sum goes to partials (the first pass of
-// the dot product p^T (W^T y)).
-__device__ double block_sum(double v);
-
-template <typename T, bool DOT>
-__global__ __launch_bounds__(kBlock) void wavelet_ana_kernel(T* __restrict__ X,
-                                                             const T* __restrict__ p,
-                                                             double* __restrict__ partials,
-                                                             int J, int64_t slab_) {
-  const int64_t slab = slab_;
-  const int64_t col = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int N = 1 << J;
-  const int64_t off = (int64_t)blockIdx.y * (N + 1) * slab + col;
-  double acc = 0.0;
-  if (col < slab) {
-    T* base = X + off;
-    auto fin = [&](int r, T v) {
-      if constexpr (DOT) acc += (double)p[off + (int64_t)r * slab] * (double)v;
-    };
-    if (J == 0) {
-      fin(0, base[0]);
-      fin(N, base[(int64_t)N * slab]);
-    }
-    for (int l = J; l >= 1; --l) {
-      const int s = N >> l;
-      const T c = (T)exp2(0.5 * (double)l);
-      T e_old = base[0];
-      T e_acc = e_old;
-      for (int m = s; m < N; m += 2 * s) {
-        const T yo = base[(int64_t)m * slab];
-        const T r_old = base[(int64_t)(m + s) * slab];
-        const T v = c * ((yo - T(boundary_weight(m - s, N)) * e_old) -
-                         T(boundary_weight(m + s, N)) * r_old);
-        base[(int64_t)m * slab] = v;
-        fin(m, v);
-        e_acc += T(0.5) * yo;
-        base[(int64_t)(m - s) * slab] = e_acc;
-        if (l == 1) fin(0, e_acc);
-        e_old = r_old;
-        e_acc = r_old + T(0.5) * yo;
-      }
-      base[(int64_t)N * slab] = e_acc;
-      if (l == 1) fin(N, e_acc);
-    }
-  }
-  if constexpr (DOT) {
-    acc = block_sum(acc);
-    if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
-  }
-}
-
 // ------------------------------------------------- wavelet, whole columns in LDS
 //
 // For FP64 time axes of at most 2^kLdsJMax intervals a workgroup holds whole
@@ -344,94 +289,6 @@ __global__ __launch_bounds__(kLdsThreads) void wavelet_syn_lds_kernel(const T* s
       }
     }
     __syncthreads();  // the next group's rows overwrite sh
-  }
-}
-
-template <typename T, bool DOT, int JMAX>
-__global__ __launch_bounds__(kLdsThreads) void wavelet_ana_lds_kernel(T* __restrict__ X,
-                                                                      const T* __restrict__ p,
-                                                                      double* __restrict__ partials,
-                                                                      int J, int64_t slab_) {
-  constexpr int C = lds_cols<T>();
-  constexpr int RG = kLdsThreads / C;
-  constexpr int BS = DOT ? kBatch / 2 : kBatch;  // two loads per row with DOT
-  __shared__ T sh[((1 << JMAX) + 1) * C];
-  const int64_t slab = slab_;
-  const int N = 1 << J;
-  const int c = threadIdx.x % C, g = threadIdx.x / C;
-  const int64_t groups = (slab + C - 1) / C;
-  double acc = 0.0;
-  for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
-    const int64_t col = grp * C + c;
-    const bool ok = col < slab;
-    const int64_t off = (int64_t)blockIdx.y * (N + 1) * slab + col;
-#pragma unroll 1
-    for (int r0 = g; r0 <= N; r0 += kBatch * RG) {
-      T v[kBatch];
-#pragma unroll
-      for (int i = 0; i < kBatch; ++i) {
-        const int r = r0 + i * RG;
-        v[i] = ok && r <= N ? X[off + (int64_t)r * slab] : T(0);
-      }
-#pragma unroll
-      for (int i = 0; i < kBatch; ++i) {
-        const int r = r0 + i * RG;
-        if (r <= N) sh[r * C + c] = v[i];
-      }
-    }
-    __syncthreads();
-    for (int l = J; l >= 1; --l) {
-      const int s = N >> l;
-      const T cl = (T)exp2(0.5 * (double)l);
-      const int items = 1 << (l - 1);
-      const LevelRun run = level_run(items, g, RG);
-      T hl = T(0), hr = T(0);
-      if (run.k0 < run.k1) {
-        if (run.k0 > 0) hl = sh[(2 * run.k0 - 1) * s * C + c];
-        hr = sh[2 * run.k1 * s * C + c];
-      }
-      __syncthreads();
-      if (run.k0 < run.k1) {
-        T e_old = sh[2 * run.k0 * s * C + c];
-        T e_acc = run.k0 > 0 ? e_old + T(0.5) * hl : e_old;
-        for (int k = run.k0; k < run.k1; ++k) {
-          const int m = (2 * k + 1) * s;
-          const T yo = sh[m * C + c];
-          const T r_old = k + 1 < run.k1 ? sh[(m + s) * C + c] : hr;
-          sh[m * C + c] = cl * ((yo - T(boundary_weight(m - s, N)) * e_old) -
-                                T(boundary_weight(m + s, N)) * r_old);
-          e_acc += T(0.5) * yo;
-          sh[(m - s) * C + c] = e_acc;
-          e_old = r_old;
-          e_acc = r_old + T(0.5) * yo;
-        }
-        if (run.k1 == items) sh[N * C + c] = e_acc;
-      }
-      __syncthreads();
-    }
-#pragma unroll 1
-    for (int r0 = g; r0 <= N; r0 += BS * RG) {
-      T v[BS], pv[BS];
-#pragma unroll
-      for (int i = 0; i < BS; ++i) {
-        const int r = r0 + i * RG;
-        v[i] = r <= N ? sh[r * C + c] : T(0);
-        if constexpr (DOT) pv[i] = ok && r <= N ? p[off + (int64_t)r * slab] : T(0);
-      }
-#pragma unroll
-      for (int i = 0; i < BS; ++i) {
-        const int r = r0 + i * RG;
-        if (ok && r <= N) {
-          X[off + (int64_t)r * slab] = v[i];
-          if constexpr (DOT) acc += (double)pv[i] * (double)v[i];
-        }
-      }
-    }
-    __syncthreads();
-  }
-  if constexpr (DOT) {
-    acc = block_sum_n<kLdsThreads>(acc);
-    if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
   }
 }
 
@@ -903,28 +760,12 @@ hipError_t launch_syn(hipStream_t s, const T* src, T* dst, T* p, const T* z, con
   return hipGetLastError();
 }
 
-// Analysis launch; returns the number of partial sums per right-hand side
-// (with DOT) through nblk.
+// Analysis launch (the one-pass kernel of wavelet_stream.hip); returns the
+// number of partial sums per right-hand side (with DOT) through nblk.
 template <typename T, bool DOT>
 hipError_t launch_ana(hipStream_t s, T* X, const T* p, double* partials, int J, int64_t slab, int nrhs,
                       int* nblk) {
-  if constexpr (sizeof(T) == 8) {
-    if (J <= kLdsJMax) {
-      const dim3 grid(lds_grid<T>(slab), nrhs);
-      *nblk = (int)grid.x;
-      if (J <= 8)
-        wavelet_ana_lds_kernel<T, DOT, 8><<<grid, kLdsThreads, 0, s>>>(X, p, partials, J, slab);
-      else if (J == 9)
-        wavelet_ana_lds_kernel<T, DOT, 9><<<grid, kLdsThreads, 0, s>>>(X, p, partials, J, slab);
-      else
-        wavelet_ana_lds_kernel<T, DOT, 10><<<grid, kLdsThreads, 0, s>>>(X, p, partials, J, slab);
-      return hipGetLastError();
-    }
-  }
-  const dim3 grid(blocks_for(slab), nrhs);
-  *nblk = (int)grid.x;
-  wavelet_ana_kernel<T, DOT><<<grid, kBlock, 0, s>>>(X, p, partials, J, slab);
-  return hipGetLastError();
+  return wavelet_ana_stream<T, DOT>(s, X, p, partials, J, slab, nrhs, nblk);
 }
 
 template <typename T>
@@ -946,9 +787,7 @@ hipError_t synthesis_update(hipStream_t s, T* p, const T* z, const double* beta,
   return launch_syn<T, true>(s, p, X, p, z, beta, J, slab, nrhs);
 }
 
-int analysis_dot_blocks(int64_t slab) {
-  return (int)std::max<int64_t>(blocks_for(slab), kLdsGrid);
-}
+int analysis_dot_blocks(int64_t slab) { return wavelet_stream_blocks(slab); }
 
 template <typename T>
 hipError_t analysis_dot(hipStream_t s, T* X, const T* p, double* partials, double* out, int J,

@@ -1,0 +1,210 @@
+// The wavelet transforms along time in one pass over the rows (gfx950).
+//
+// One thread per slab column.  The analysis W^T (Section 3.3, eq. (10), fine
+// to coarse) is a cascade of per-level lifting steps: level l consumes the
+// values of its rows (multiples of s = N / 2^l) in increasing row order, and
+// every second value it consumes completes one of its odd rows (written out:
+// final) and one of its even rows, which it passes on to level l - 1 as that
+// level's next value.  Each level keeps three values in registers (the old
+// and the accumulating value of its current even row, the pending odd row),
+// so the input is read once, in row order, and every row is written once,
+// when it becomes final.  Each level performs the operations of a level-by-
+// level sweep over the column in the same order, so the results are the same
+// value for value; only the interleaving of the levels differs.
+//
+// Rows are read in batches of kStreamBatch per thread, all issued before the
+// first is used.  The level structure is unrolled at compile time (the kernel
+// is instantiated per J), so the level states are plain registers.
+//
+// The dot product that PCG needs after the analysis, p^T (W^T y) with y the
+// operator applied to X = W p, is taken as X^T y = (W p)^T y, the same number
+// in exact arithmetic: X is still resident, and X^T y sums over the rows in
+// the order they are read, where p^T (W^T y) would pair every output row with
+// a row of p in the scattered order in which the outputs become final.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace stp {
+
+namespace {
+
+constexpr int kStreamBlock = 256;
+constexpr int kStreamBatch = 8;
+
+template <typename T, int J>
+struct AnaState {
+  T eo[J];  // old value of the level's current even row
+  T ea[J];  // its value with the contributions of the odd rows seen so far
+  T yo[J];  // the pending odd row
+  int k[J]; // values consumed by the level
+};
+
+// Writes the final value v of row r.
+template <typename T, bool DOT>
+struct AnaOut {
+  T* x;
+  int64_t slab;
+  __device__ __forceinline__ void operator()(int r, T v) { x[(int64_t)r * slab] = v; }
+};
+
+// Level J - t consumes value x (its k-th, row k s).
+template <typename T, bool DOT, int J, int t>
+__device__ __forceinline__ void ana_feed(AnaState<T, J>& st, T x, AnaOut<T, DOT>& out) {
+  constexpr int l = J - t;
+  constexpr int N = 1 << J;
+  constexpr int s = 1 << t;
+  constexpr int last = 1 << l;
+  const int i = st.k[t]++;
+  if (i == 0) {
+    st.eo[t] = x;
+    st.ea[t] = x;
+    return;
+  }
+  if (i & 1) {
+    st.yo[t] = x;
+    return;
+  }
+  // x is the old value of the even row i s; the odd row (i - 1) s is final
+  const T c = (T)exp2(0.5 * (double)l);
+  const T yo = st.yo[t];
+  const T wl = i == 2 ? T(1) : T(0.5);     // boundary weights of rows 0 and N
+  const T wr = i == last ? T(1) : T(0.5);
+  out((i - 1) * s, c * ((yo - wl * st.eo[t]) - wr * x));
+  const T e = st.ea[t] + T(0.5) * yo;      // the even row (i - 2) s, done at this level
+  st.eo[t] = x;
+  st.ea[t] = x + T(0.5) * yo;
+  if constexpr (l == 1) {
+    out(0, e);
+    out(N, st.ea[t]);
+  } else {
+    ana_feed<T, DOT, J, t + 1>(st, e, out);
+  }
+}
+
+// After the last input row: level J - t passes its last even row (row N) on.
+template <typename T, bool DOT, int J, int t>
+__device__ __forceinline__ void ana_flush(AnaState<T, J>& st, AnaOut<T, DOT>& out) {
+  if constexpr (t + 1 < J) {
+    ana_feed<T, DOT, J, t + 1>(st, st.ea[t], out);
+    ana_flush<T, DOT, J, t + 1>(st, out);
+  }
+}
+
+__device__ double stream_block_sum(double v) {
+  __shared__ double part[kStreamBlock / 64];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) part[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kStreamBlock / 64; ++k) t += part[k];
+  __syncthreads();
+  return t;
+}
+
+// In place on Y (nrhs blocks of N + 1 slabs); with DOT the block's share of
+// Xs^T Y (Y before the transform) goes to partials[rhs * gridDim.x + block].
+template <typename T, bool DOT, int J>
+__global__ __launch_bounds__(kStreamBlock) void wavelet_ana_stream_kernel(
+    T* __restrict__ Y, const T* __restrict__ Xs, double* __restrict__ partials, int64_t slab) {
+  constexpr int N = 1 << J;
+  const int64_t col = (int64_t)blockIdx.x * kStreamBlock + threadIdx.x;
+  double acc = 0.0;
+  if (col < slab) {
+    const int64_t off = (int64_t)blockIdx.y * (N + 1) * slab + col;
+    AnaOut<T, DOT> out;
+    out.x = Y + off;
+    out.slab = slab;
+    const T* xs = DOT ? Xs + off : nullptr;
+    AnaState<T, J> st;
+#pragma unroll
+    for (int t = 0; t < J; ++t) st.k[t] = 0;
+#pragma unroll 1
+    for (int r0 = 0; r0 <= N; r0 += kStreamBatch) {
+      T v[kStreamBatch], w[kStreamBatch];
+#pragma unroll
+      for (int b = 0; b < kStreamBatch; ++b) {
+        v[b] = r0 + b <= N ? out.x[(int64_t)(r0 + b) * slab] : T(0);
+        if constexpr (DOT) w[b] = r0 + b <= N ? xs[(int64_t)(r0 + b) * slab] : T(0);
+      }
+      const int nb = min(kStreamBatch, N + 1 - r0);
+      if constexpr (DOT) {
+#pragma unroll
+        for (int b = 0; b < kStreamBatch; ++b) acc += (double)w[b] * (double)v[b];  // 0 past N
+      }
+#pragma unroll 1
+      for (int b = 0; b < nb; ++b) {
+        const T x = v[0];
+#pragma unroll
+        for (int q = 0; q + 1 < kStreamBatch; ++q) v[q] = v[q + 1];
+        ana_feed<T, DOT, J, 0>(st, x, out);
+      }
+    }
+    ana_flush<T, DOT, J, 0>(st, out);
+  }
+  if constexpr (DOT) {
+    acc = stream_block_sum(acc);
+    if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
+  }
+}
+
+// J = 0: W is the identity on the two rows; only the dot.
+template <typename T>
+__global__ __launch_bounds__(kStreamBlock) void dot_rows2_kernel(const T* __restrict__ Y,
+                                                                  const T* __restrict__ Xs,
+                                                                  double* __restrict__ partials,
+                                                                  int64_t slab) {
+  const int64_t col = (int64_t)blockIdx.x * kStreamBlock + threadIdx.x;
+  double acc = 0.0;
+  if (col < slab) {
+    const int64_t off = (int64_t)blockIdx.y * 2 * slab + col;
+    acc = (double)Xs[off] * (double)Y[off] + (double)Xs[off + slab] * (double)Y[off + slab];
+  }
+  acc = stream_block_sum(acc);
+  if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
+}
+
+template <typename T, bool DOT, int J>
+hipError_t launch_ana_stream_j(hipStream_t s, T* X, const T* p, double* partials, int64_t slab,
+                               int nrhs, int* nblk) {
+  const dim3 grid((unsigned)((slab + kStreamBlock - 1) / kStreamBlock), nrhs);
+  *nblk = (int)grid.x;
+  wavelet_ana_stream_kernel<T, DOT, J><<<grid, kStreamBlock, 0, s>>>(X, p, partials, slab);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T, bool DOT>
+hipError_t wavelet_ana_stream(hipStream_t s, T* X, const T* p, double* partials, int J,
+                              int64_t slab, int nrhs, int* nblk) {
+  if (J == 0) {
+    const dim3 grid((unsigned)((slab + kStreamBlock - 1) / kStreamBlock), nrhs);
+    *nblk = (int)grid.x;
+    if constexpr (DOT) dot_rows2_kernel<T><<<grid, kStreamBlock, 0, s>>>(X, p, partials, slab);
+    return hipGetLastError();
+  }
+  switch (J) {
+#define STP_J(j) \
+  case j: return launch_ana_stream_j<T, DOT, j>(s, X, p, partials, slab, nrhs, nblk);
+    STP_J(1) STP_J(2) STP_J(3) STP_J(4) STP_J(5) STP_J(6) STP_J(7)
+    STP_J(8) STP_J(9) STP_J(10) STP_J(11) STP_J(12) STP_J(13) STP_J(14)
+#undef STP_J
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int wavelet_stream_blocks(int64_t slab) { return (int)((slab + kStreamBlock - 1) / kStreamBlock); }
+
+template hipError_t wavelet_ana_stream<double, false>(hipStream_t, double*, const double*, double*,
+                                                      int, int64_t, int, int*);
+template hipError_t wavelet_ana_stream<double, true>(hipStream_t, double*, const double*, double*,
+                                                     int, int64_t, int, int*);
+template hipError_t wavelet_ana_stream<float, false>(hipStream_t, float*, const float*, double*,
+                                                     int, int64_t, int, int*);
+template hipError_t wavelet_ana_stream<float, true>(hipStream_t, float*, const float*, double*, int,
+                                                    int64_t, int, int*);
+
+}  // namespace stp
