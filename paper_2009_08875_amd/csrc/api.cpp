@@ -152,6 +152,7 @@ stp_status plan_context(Arena& ar, stp_ctx* c) {
   STP_TRY(ar.get(&c->u, vec));
   STP_TRY(ar.get(&c->sigma, c->rows));
   STP_TRY(ar.get(&c->rhoref, c->nrhs));
+  STP_TRY(ar.get(&c->syn_order, (int64_t)c->rows_per));
   STP_TRY(ar.get(&c->partials, (int64_t)c->nrhs * std::max(1024, analysis_dot_blocks(c->slab))));
   STP_TRY(ar.get(&c->tolv, c->nrhs));
   STP_TRY(ar.get(&c->sc.rho, c->nrhs));
@@ -370,9 +371,9 @@ stp_status S_apply(stp_ctx* c, Ops<T>& o, const T* X, T* out, int nrhs) {
 // out = S-hat p = W^T S W p (eq. (11)).
 template <typename T>
 stp_status Shat_apply(stp_ctx* c, Ops<T>& o, const T* p, T* out, int nrhs) {
-  HIP_TRY(synthesis<T>(c->stream, p, o.X, c->J, c->slab, nrhs));
+  HIP_TRY(synthesis<T>(c->stream, p, o.X, c->J, c->slab, nrhs, c->syn_order));
   STP_TRY(S_apply<T>(c, o, o.X, out, nrhs));
-  HIP_TRY(wavelet<T>(c->stream, out, c->J, c->slab, nrhs, false));
+  HIP_TRY(wavelet<T>(c->stream, out, c->J, c->slab, nrhs, false, c->syn_order));
   return STP_OK;
 }
 
@@ -383,7 +384,8 @@ template <typename T>
 stp_status Shat_iteration(stp_ctx* c, Ops<T>& o, PcgVecs<T>& v) {
   // z, p in; p, X out
   STP_TRY(timed_launch(c, STP_KERNEL_SYN_UPDATE, row_bytes<T>(c, c->rows, 4.0), [&] {
-    return synthesis_update<T>(c->stream, v.p, v.z, c->sc.beta, o.X, c->J, c->slab, c->nrhs);
+    return synthesis_update<T>(c->stream, v.p, v.z, c->sc.beta, o.X, c->J, c->slab, c->nrhs,
+                               c->syn_order);
   }));
   STP_TRY(S_apply<T>(c, o, o.X, v.q, c->nrhs));
   // q (= S X), X in; q = W^T S X out, p^T q = X^T S X (X = W p)
@@ -589,13 +591,13 @@ stp_status finish_unit(stp_ctx* c) {
   double* hs = c->h_stats;
   int* hi = (int*)(c->h_stats + 2 * nr);
   if (c->prec == STP_FP64) {
-    HIP_TRY(synthesis<double>(c->stream, c->pcg64.w, c->u, c->J, c->slab, nr));
+    HIP_TRY(synthesis<double>(c->stream, c->pcg64.w, c->u, c->J, c->slab, nr, c->syn_order));
     HIP_TRY(hipMemcpyAsync(hs, c->sc.rho, sizeof(double) * nr, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(hs + nr, c->sc.rho0, sizeof(double) * nr, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(hi, c->sc.its, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(hi + nr, c->sc.status, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
   } else {
-    HIP_TRY(synthesis<double>(c->stream, c->w64, c->u, c->J, c->slab, nr));
+    HIP_TRY(synthesis<double>(c->stream, c->w64, c->u, c->J, c->slab, nr, c->syn_order));
     HIP_TRY(hipMemcpyAsync(hs, c->ms.rel, sizeof(double) * nr, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(hi, c->ms.inner_its, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(hi + nr, c->ms.status, sizeof(int) * nr, hipMemcpyDeviceToHost, c->stream));
@@ -673,7 +675,7 @@ stp_status drive_begin(stp_ctx* c, const double* tol, const stp_ctx* coarse) {
   HIP_TRY(hipEventRecord(c->ev0, c->stream));
   HIP_TRY(hipMemcpyAsync(c->tolv, c->h_tol, sizeof(double) * nr, hipMemcpyHostToDevice, c->stream));
   STP_TRY(rhs_apply(c, c->fhat));
-  HIP_TRY(wavelet<double>(c->stream, c->fhat, c->J, c->slab, nr, false));
+  HIP_TRY(wavelet<double>(c->stream, c->fhat, c->J, c->slab, nr, false, c->syn_order));
   if (c->prec == STP_FP64) {
     if (coarse)
       STP_TRY(pcg_init_from(c, coarse, c->tolv));
@@ -952,7 +954,12 @@ stp_status stp_create(int J, int K, int nrhs, int precision, const stp_options* 
     set_error("pinned host allocation or event creation failed");
     return fail(STP_E_DEVICE);
   }
+  // the read order of the one-pass synthesis (the host copy lives until the
+  // synchronisation below)
+  const std::vector<int> order = synthesis_read_order(J);
   if (fill_level_sigma(c->stream, c->sigma, J, nrhs) != hipSuccess ||
+      hipMemcpyAsync(c->syn_order, order.data(), sizeof(int) * order.size(),
+                     hipMemcpyHostToDevice, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
     set_error("initialisation kernels failed");
     return fail(STP_E_DEVICE);
@@ -1137,11 +1144,11 @@ stp_status apply_op_t(stp_ctx* c, int op, const double* in_dev, double* out_dev)
   switch (op) {
     case STP_OP_W:
       HIP_TRY(copy<T>(c->stream, in_t, out_t, c->per_rhs));
-      HIP_TRY(wavelet<T>(c->stream, out_t, J, c->slab, 1, true));
+      HIP_TRY(wavelet<T>(c->stream, out_t, J, c->slab, 1, true, c->syn_order));
       break;
     case STP_OP_WT:
       HIP_TRY(copy<T>(c->stream, in_t, out_t, c->per_rhs));
-      HIP_TRY(wavelet<T>(c->stream, out_t, J, c->slab, 1, false));
+      HIP_TRY(wavelet<T>(c->stream, out_t, J, c->slab, 1, false, c->syn_order));
       break;
     case STP_OP_S:
       STP_TRY(S_apply<T>(c, o, in_t, out_t, 1));

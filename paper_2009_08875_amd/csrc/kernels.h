@@ -8,6 +8,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "layout.h"
 
 namespace stp {
@@ -65,6 +67,10 @@ hipError_t mg_post_stream(hipStream_t s, const T* xin, const T* b, const T* ec, 
 // on X, 0 <= J <= 14; with DOT the first pass of p^T X (X before the
 // transform), one partial per block of wavelet_stream_blocks(slab) and
 // right-hand side, to partials.
+template <typename T, bool UPD>
+hipError_t wavelet_syn_stream(hipStream_t s, const T* src, T* dst, T* p, const T* z,
+                              const double* beta, const int* order, int J, int64_t slab,
+                              int nrhs);
 template <typename T, bool DOT>
 hipError_t wavelet_ana_stream(hipStream_t s, T* X, const T* p, double* partials, int J,
                               int64_t slab, int nrhs, int* nblk);
@@ -116,15 +122,21 @@ hipError_t apply_M(hipStream_t s, const T* x, T* y, int K, int rows);
 // acts on every element of a time row alike, so it takes the row length
 // (slab: slab_elems(K) in 2D, slab3_elems(K) in 3D).
 template <typename T>
-hipError_t wavelet(hipStream_t s, T* X, int J, int64_t slab, int nrhs, bool synthesis);
-// dst = W src (src == dst allowed; for J = 0 a copy).
+hipError_t wavelet(hipStream_t s, T* X, int J, int64_t slab, int nrhs, bool synthesis,
+                   const int* order);
+// dst = W src (src == dst allowed; for J = 0 a copy).  `order`: the device
+// copy of synthesis_read_order(J).
 template <typename T>
-hipError_t synthesis(hipStream_t s, const T* src, T* dst, int J, int64_t slab, int nrhs);
+hipError_t synthesis(hipStream_t s, const T* src, T* dst, int J, int64_t slab, int nrhs,
+                     const int* order);
 // X = W p after the conjugate-gradient update p = z + beta_b p (p is updated
 // in place; X must not alias p, z).
 template <typename T>
 hipError_t synthesis_update(hipStream_t s, T* p, const T* z, const double* beta, T* X, int J,
-                            int64_t slab, int nrhs);
+                            int64_t slab, int nrhs, const int* order);
+// The rows 0..2^J in the order in which the one-pass synthesis reads their
+// coefficients (wavelet_stream.hip).
+std::vector<int> synthesis_read_order(int J);
 // Y = W^T Y in place, and out_b = Ws_b^T Y_b with Y before the transform
 // (FP64, deterministic).  With Ws = W p this is p^T (W^T Y), the dot PCG
 // needs.  partials holds nrhs * analysis_dot_blocks(slab) values.

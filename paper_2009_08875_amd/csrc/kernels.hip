@@ -89,209 +89,6 @@ __global__ __launch_bounds__(kBlock) void apply_AM_kernel(const T* __restrict__ 
   }
 }
 
-// ------------------------------------------------------------------ wavelet
-//
-// One thread per slab element (a column along time); the column is processed
-// level by level in place, each level as a single left-to-right pass that
-// keeps the old value of the current even node in registers.
-__device__ inline double boundary_weight(int e, int N) { return (e == 0 || e == N) ? 1.0 : 0.5; }
-
-// Synthesis W (coarse to fine), one thread per column of the slab.  At
-// level l the odd multiples m of s = N / 2^l are touched for the first time:
-// their coefficient d is read from src; the even neighbours (multiples of
-// 2s) come from dst, where coarser levels left them (rows 0 and N are first
-// touched at level 1).  src == dst runs in place.  With UPD the first touch
-// of a row also performs the conjugate-gradient update p = z + beta p: src is
-// p, which receives the updated value, and the updated value is transformed.
-template <typename T, bool UPD>
-__global__ __launch_bounds__(kBlock) void wavelet_syn_kernel(const T* src, T* dst, T* p,
-                                                             const T* __restrict__ z,
-                                                             const double* __restrict__ beta,
-                                                             int J, int64_t slab_) {
-  const int64_t slab = slab_;
-  const int64_t col = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (col >= slab) return;
-  const int N = 1 << J;
-  const int64_t off = (int64_t)blockIdx.y * (N + 1) * slab + col;
-  const T* sb = src + off;
-  T* db = dst + off;
-  const double bt = UPD ? beta[blockIdx.y] : 0.0;
-  auto first = [&](int r) -> T {
-    const int64_t o = (int64_t)r * slab;
-    if constexpr (UPD) {
-      const T v = (T)((double)z[off + o] + bt * (double)p[off + o]);
-      p[off + o] = v;
-      return v;
-    } else {
-      return sb[o];
-    }
-  };
-  if (J == 0) {
-    const T v0 = first(0), v1 = first(N);
-    db[0] = v0;
-    db[(int64_t)N * slab] = v1;
-    return;
-  }
-  for (int l = 1; l <= J; ++l) {
-    const int s = N >> l;
-    const T c = (T)exp2(0.5 * (double)l);
-    T e_old = l == 1 ? first(0) : db[0];
-    T e_acc = e_old;
-    for (int m = s; m < N; m += 2 * s) {
-      const T d = first(m);
-      const T r_old = l == 1 ? first(N) : db[(int64_t)(m + s) * slab];
-      db[(int64_t)m * slab] = T(0.5) * (e_old + r_old) + c * d;
-      e_acc -= c * T(boundary_weight(m - s, N)) * d;
-      db[(int64_t)(m - s) * slab] = e_acc;
-      e_old = r_old;
-      e_acc = r_old - c * T(boundary_weight(m + s, N)) * d;
-    }
-    db[(int64_t)N * slab] = e_acc;
-  }
-}
-
-// ------------------------------------------------- wavelet, whole columns in LDS
-//
-// For FP64 time axes of at most 2^kLdsJMax intervals a workgroup holds whole
-// columns: lds_cols<T>() adjacent slab columns (one 128-byte line per row)
-// for all N + 1 rows.  Each row is read from HBM once and written once, and
-// every level runs in LDS, where the column kernels above re-read and
-// re-write rows level by level.  Within a level the odd rows of a column are
-// cut into runs of consecutive odd rows, one run per thread; a run is
-// processed left to right with the operations the column kernels apply to a
-// whole level, in the same order, and the two values it shares with the
-// neighbouring runs -- the odd row just left of it and the even row just
-// right of it -- are read before the level starts.  The fused dot sums each
-// thread's rows in row order, then the workgroup in a fixed order.
-constexpr int kLdsJMax = 10;
-constexpr int kLdsThreads = 1024;
-constexpr int kLdsGrid = 2048;  // workgroups per right-hand side, at most
-constexpr int kBatch = 8;       // rows a thread loads or stores at once
-template <typename T>
-constexpr int lds_cols() {
-  return 128 / (int)sizeof(T);
-}
-
-template <int NT>
-__device__ double block_sum_n(double v) {
-  __shared__ double part[NT / 64];
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) part[wv] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < NT / 64; ++k) t += part[k];
-  }
-  __syncthreads();
-  return t;
-}
-
-// Runs of one level: thread g of a column takes odd rows (2k + 1) s for k in
-// [k0, k1) of the `items` odd rows.
-struct LevelRun {
-  int k0, k1;
-};
-__device__ __forceinline__ LevelRun level_run(int items, int g, int threads_per_col) {
-  const int per = (items + threads_per_col - 1) / threads_per_col;
-  const int k0 = min(g * per, items);
-  return {k0, min(k0 + per, items)};
-}
-
-template <typename T, bool UPD, int JMAX>
-__global__ __launch_bounds__(kLdsThreads) void wavelet_syn_lds_kernel(const T* src, T* dst, T* p,
-                                                                      const T* __restrict__ z,
-                                                                      const double* __restrict__ beta,
-                                                                      int J, int64_t slab_) {
-  constexpr int C = lds_cols<T>();
-  constexpr int RG = kLdsThreads / C;  // threads per column
-  constexpr int B = UPD ? kBatch / 2 : kBatch;  // two loads per row with UPD
-  __shared__ T sh[((1 << JMAX) + 1) * C];
-  const int64_t slab = slab_;
-  const int N = 1 << J;
-  const int c = threadIdx.x % C, g = threadIdx.x / C;
-  const double bt = UPD ? beta[blockIdx.y] : 0.0;
-  const int64_t groups = (slab + C - 1) / C;
-  for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
-    const int64_t col = grp * C + c;
-    const bool ok = col < slab;
-    const int64_t off = (int64_t)blockIdx.y * (N + 1) * slab + col;
-    // every row's coefficient (with UPD: p = z + beta p, written back); a
-    // thread issues B rows of loads before it uses the first
-#pragma unroll 1
-    for (int r0 = g; r0 <= N; r0 += B * RG) {
-      T v[B];
-#pragma unroll
-      for (int i = 0; i < B; ++i) {
-        const int r = r0 + i * RG;
-        v[i] = T(0);
-        if (ok && r <= N) {
-          const int64_t o = off + (int64_t)r * slab;
-          if constexpr (UPD) {
-            v[i] = (T)((double)z[o] + bt * (double)p[o]);
-          } else {
-            v[i] = src[o];
-          }
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < B; ++i) {
-        const int r = r0 + i * RG;
-        if (r <= N) {
-          sh[r * C + c] = v[i];
-          if constexpr (UPD) {
-            if (ok) p[off + (int64_t)r * slab] = v[i];
-          }
-        }
-      }
-    }
-    __syncthreads();
-    for (int l = 1; l <= J; ++l) {
-      const int s = N >> l;
-      const T cl = (T)exp2(0.5 * (double)l);
-      const int items = 1 << (l - 1);
-      const LevelRun run = level_run(items, g, RG);
-      T hl = T(0), hr = T(0);
-      if (run.k0 < run.k1) {
-        if (run.k0 > 0) hl = sh[(2 * run.k0 - 1) * s * C + c];
-        hr = sh[2 * run.k1 * s * C + c];
-      }
-      __syncthreads();
-      if (run.k0 < run.k1) {
-        T e_old = sh[2 * run.k0 * s * C + c];
-        T e_acc = run.k0 > 0 ? e_old - cl * T(boundary_weight(2 * run.k0 * s, N)) * hl : e_old;
-        for (int k = run.k0; k < run.k1; ++k) {
-          const int m = (2 * k + 1) * s;
-          const T d = sh[m * C + c];
-          const T r_old = k + 1 < run.k1 ? sh[(m + s) * C + c] : hr;
-          sh[m * C + c] = T(0.5) * (e_old + r_old) + cl * d;
-          e_acc -= cl * T(boundary_weight(m - s, N)) * d;
-          sh[(m - s) * C + c] = e_acc;
-          e_old = r_old;
-          e_acc = r_old - cl * T(boundary_weight(m + s, N)) * d;
-        }
-        if (run.k1 == items) sh[N * C + c] = e_acc;
-      }
-      __syncthreads();
-    }
-#pragma unroll 1
-    for (int r0 = g; r0 <= N; r0 += B * RG) {
-      T v[B];
-#pragma unroll
-      for (int i = 0; i < B; ++i) {
-        const int r = r0 + i * RG;
-        v[i] = r <= N ? sh[r * C + c] : T(0);
-      }
-#pragma unroll
-      for (int i = 0; i < B; ++i) {
-        const int r = r0 + i * RG;
-        if (ok && r <= N) dst[off + (int64_t)r * slab] = v[i];
-      }
-    }
-    __syncthreads();  // the next group's rows overwrite sh
-  }
-}
-
 // ------------------------------------------------------------ reductions
 
 __device__ double block_sum(double v) {
@@ -729,39 +526,7 @@ hipError_t apply_M(hipStream_t s, const T* x, T* y, int K, int rows) {
   return hipGetLastError();
 }
 
-// Workgroups of the LDS-resident transform per right-hand side.
-template <typename T>
-int lds_grid(int64_t slab) {
-  const int64_t groups = (slab + lds_cols<T>() - 1) / lds_cols<T>();
-  return (int)std::min<int64_t>(groups, kLdsGrid);
-}
-
-// Synthesis launch: in FP64 whole columns in LDS for J <= kLdsJMax (the LDS
-// array is sized for 2^8, 2^9 or 2^10 intervals), one thread per column
-// otherwise.  In FP32 the column kernels measured as fast or faster.
-template <typename T, bool UPD>
-hipError_t launch_syn(hipStream_t s, const T* src, T* dst, T* p, const T* z, const double* beta,
-                      int J, int64_t slab, int nrhs) {
-  if constexpr (sizeof(T) == 8) {
-    if (J <= kLdsJMax) {
-      const dim3 grid(lds_grid<T>(slab), nrhs);
-      if (J <= 8)
-        wavelet_syn_lds_kernel<T, UPD, 8><<<grid, kLdsThreads, 0, s>>>(src, dst, p, z, beta, J, slab);
-      else if (J == 9)
-        wavelet_syn_lds_kernel<T, UPD, 9><<<grid, kLdsThreads, 0, s>>>(src, dst, p, z, beta, J, slab);
-      else
-        wavelet_syn_lds_kernel<T, UPD, 10><<<grid, kLdsThreads, 0, s>>>(src, dst, p, z, beta, J,
-                                                                        slab);
-      return hipGetLastError();
-    }
-  }
-  const dim3 grid(blocks_for(slab), nrhs);
-  wavelet_syn_kernel<T, UPD><<<grid, kBlock, 0, s>>>(src, dst, p, z, beta, J, slab);
-  return hipGetLastError();
-}
-
-// Analysis launch (the one-pass kernel of wavelet_stream.hip); returns the
-// number of partial sums per right-hand side (with DOT) through nblk.
+// The wavelet launches (the one-pass kernels of wavelet_stream.hip).
 template <typename T, bool DOT>
 hipError_t launch_ana(hipStream_t s, T* X, const T* p, double* partials, int J, int64_t slab, int nrhs,
                       int* nblk) {
@@ -769,22 +534,25 @@ hipError_t launch_ana(hipStream_t s, T* X, const T* p, double* partials, int J, 
 }
 
 template <typename T>
-hipError_t wavelet(hipStream_t s, T* X, int J, int64_t slab, int nrhs, bool synthesis) {
+hipError_t wavelet(hipStream_t s, T* X, int J, int64_t slab, int nrhs, bool synthesis,
+                   const int* order) {
   if (J == 0) return hipSuccess;
-  if (synthesis) return launch_syn<T, false>(s, X, X, nullptr, nullptr, nullptr, J, slab, nrhs);
+  if (synthesis)
+    return wavelet_syn_stream<T, false>(s, X, X, nullptr, nullptr, nullptr, order, J, slab, nrhs);
   int nblk = 0;
   return launch_ana<T, false>(s, X, nullptr, nullptr, J, slab, nrhs, &nblk);
 }
 
 template <typename T>
-hipError_t synthesis(hipStream_t s, const T* src, T* dst, int J, int64_t slab, int nrhs) {
-  return launch_syn<T, false>(s, src, dst, nullptr, nullptr, nullptr, J, slab, nrhs);
+hipError_t synthesis(hipStream_t s, const T* src, T* dst, int J, int64_t slab, int nrhs,
+                     const int* order) {
+  return wavelet_syn_stream<T, false>(s, src, dst, nullptr, nullptr, nullptr, order, J, slab, nrhs);
 }
 
 template <typename T>
 hipError_t synthesis_update(hipStream_t s, T* p, const T* z, const double* beta, T* X, int J,
-                            int64_t slab, int nrhs) {
-  return launch_syn<T, true>(s, p, X, p, z, beta, J, slab, nrhs);
+                            int64_t slab, int nrhs, const int* order) {
+  return wavelet_syn_stream<T, true>(s, p, X, p, z, beta, order, J, slab, nrhs);
 }
 
 int analysis_dot_blocks(int64_t slab) { return wavelet_stream_blocks(slab); }
@@ -944,11 +712,10 @@ hipError_t fill_level_sigma(hipStream_t s, double* sigma, int J, int nrhs) {
 #define STP_INSTANTIATE(T)                                                                        \
   template hipError_t apply_A<T>(hipStream_t, const T*, T*, int, int, const SpaceOp&);            \
   template hipError_t apply_M<T>(hipStream_t, const T*, T*, int, int);                            \
-  template hipError_t wavelet<T>(hipStream_t, T*, int, int64_t, int, bool);                       \
-  template hipError_t synthesis<T>(hipStream_t, const T*, T*, int, int64_t, int);                 \
+  template hipError_t wavelet<T>(hipStream_t, T*, int, int64_t, int, bool, const int*);           \
+  template hipError_t synthesis<T>(hipStream_t, const T*, T*, int, int64_t, int, const int*);     \
   template hipError_t synthesis_update<T>(hipStream_t, T*, const T*, const double*, T*, int,      \
-                                          int64_t,                                                \
-                                          int);                                                  \
+                                          int64_t, int, const int*);                              \
   template hipError_t analysis_dot<T>(hipStream_t, T*, const T*, double*, double*, int, int64_t, \
                                       int);                                                       \
   template hipError_t dot<T>(hipStream_t, const T*, const T*, int64_t, int, double*, double*);    \

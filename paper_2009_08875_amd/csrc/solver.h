@@ -88,6 +88,7 @@ struct stp_ctx {
 
   double* sigma = nullptr;  // 2^level per time row (K_X)
   double* rhoref = nullptr; // f-hat^T K_X f-hat per right-hand side (PCG from an initial guess)
+  int* syn_order = nullptr;  // synthesis_read_order(J) on the device
   std::vector<stp_ctx*> nest;  // nested iteration: meshes (J - d, K - d), d = 1..nest.size()
   double* partials = nullptr;
   stp::PcgScalars sc{};

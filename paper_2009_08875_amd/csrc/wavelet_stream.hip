@@ -21,7 +21,20 @@
 // in exact arithmetic: X is still resident, and X^T y sums over the rows in
 // the order they are read, where p^T (W^T y) would pair every output row with
 // a row of p in the scattered order in which the outputs become final.
+//
+// The synthesis W (coarse to fine) runs the same way in the other direction:
+// level 0 hands rows 0 and N to level 1, and level l, on receiving the value
+// of its even row m + s, reads the coefficient of its odd row m and hands the
+// finished rows m - s and m to level l + 1; level J's rows are final and are
+// written in row order.  The coefficients are consumed in a fixed order of the
+// rows (the order in which this cascade first needs them, the same for every
+// column), which the host computes once per J by running the cascade; the
+// kernel reads them in that order, in batches, so the reads are prefetched
+// like the analysis's although they are not in row order.  With the update,
+// the batch forms p = z + beta p and writes p back as it loads.
 #include <hip/hip_runtime.h>
+
+#include <vector>
 
 #include "kernels.h"
 
@@ -166,6 +179,142 @@ __global__ __launch_bounds__(kStreamBlock) void dot_rows2_kernel(const T* __rest
   if (threadIdx.x == 0) partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
 }
 
+// ---------------------------------------------------------------- synthesis
+
+template <typename T, bool UPD, int J>
+struct SynState {
+  T eo[J + 1];  // level l: old value of its current even row
+  T ea[J + 1];  // and that value with the contributions of the odd rows seen
+  int k[J + 1]; // values received by level l
+  // coefficients in the read order, kStreamBatch at a time
+  T ring[kStreamBatch];
+  int left;     // coefficients in the ring
+  int next;     // position in the read order of the next batch
+  int orow;     // next output row
+  const int* order;
+  const T* src;
+  T* p;
+  const T* z;
+  double beta;
+  T* dst;
+  int64_t slab;
+
+  __device__ __forceinline__ T input() {
+    if (left == 0) {
+      constexpr int N = 1 << J;
+      T a[kStreamBatch], b[kStreamBatch];
+      int rows[kStreamBatch];
+#pragma unroll
+      for (int q = 0; q < kStreamBatch; ++q) {
+        const bool ok = next + q <= N;
+        rows[q] = ok ? order[next + q] : 0;
+        if constexpr (UPD) {
+          a[q] = ok ? z[(int64_t)rows[q] * slab] : T(0);
+          b[q] = ok ? p[(int64_t)rows[q] * slab] : T(0);
+        } else {
+          a[q] = ok ? src[(int64_t)rows[q] * slab] : T(0);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kStreamBatch; ++q) {
+        if constexpr (UPD) {
+          ring[q] = (T)((double)a[q] + beta * (double)b[q]);
+          if (next + q <= N) p[(int64_t)rows[q] * slab] = ring[q];
+        } else {
+          ring[q] = a[q];
+        }
+      }
+      left = min(kStreamBatch, N + 1 - next);
+      next += kStreamBatch;
+    }
+    const T x = ring[0];
+#pragma unroll
+    for (int q = 0; q + 1 < kStreamBatch; ++q) ring[q] = ring[q + 1];
+    --left;
+    return x;
+  }
+  __device__ __forceinline__ void output(T v) { dst[(int64_t)(orow++) * slab] = v; }
+};
+
+// Level l receives x, the value of its k-th even row (row 2 k s, s = N / 2^l).
+template <typename T, bool UPD, int J, int l>
+__device__ __forceinline__ void syn_feed(SynState<T, UPD, J>& st, T x) {
+  if constexpr (l > J) {
+    st.output(x);
+  } else {
+    constexpr int N = 1 << J;
+    constexpr int s = N >> l;
+    const int i = st.k[l]++;
+    if (i == 0) {
+      st.eo[l] = x;
+      st.ea[l] = x;
+      return;
+    }
+    // x is the old value of the even row m + s; the odd row m comes in now
+    const int m = (2 * i - 1) * s;
+    const T c = (T)exp2(0.5 * (double)l);
+    const T d = st.input();
+    const T wl = m - s == 0 ? T(1) : T(0.5);  // boundary weights of rows 0 and N
+    const T wr = m + s == N ? T(1) : T(0.5);
+    const T odd = T(0.5) * (st.eo[l] + x) + c * d;
+    const T even = st.ea[l] - c * wl * d;      // row m - s, done at this level
+    st.eo[l] = x;
+    st.ea[l] = x - c * wr * d;
+#pragma unroll 1
+    for (int q = 0; q < 2; ++q) syn_feed<T, UPD, J, l + 1>(st, q == 0 ? even : odd);
+  }
+}
+
+// After the coarsest values: level l passes its last even row (row N) on.
+template <typename T, bool UPD, int J, int l>
+__device__ __forceinline__ void syn_flush(SynState<T, UPD, J>& st) {
+  if constexpr (l <= J) {
+    syn_feed<T, UPD, J, l + 1>(st, st.ea[l]);
+    syn_flush<T, UPD, J, l + 1>(st);
+  }
+}
+
+// dst = W src for nrhs blocks of N + 1 slabs (src == dst allowed); with UPD
+// the coefficients are p = z + beta_rhs p, written back to p (src unused).
+template <typename T, bool UPD, int J>
+__global__ __launch_bounds__(kStreamBlock) void wavelet_syn_stream_kernel(
+    const T* src, T* dst, T* p, const T* __restrict__ z, const double* __restrict__ beta,
+    const int* __restrict__ order, int64_t slab) {
+  constexpr int N = 1 << J;
+  const int64_t col = (int64_t)blockIdx.x * kStreamBlock + threadIdx.x;
+  if (col >= slab) return;
+  const int64_t off = (int64_t)blockIdx.y * (N + 1) * slab + col;
+  SynState<T, UPD, J> st;
+#pragma unroll
+  for (int l = 0; l <= J; ++l) st.k[l] = 0;
+  st.left = 0;
+  st.next = 0;
+  st.orow = 0;
+  st.order = order;
+  st.slab = slab;
+  st.dst = dst + off;
+  if constexpr (UPD) {
+    st.p = p + off;
+    st.z = z + off;
+    st.beta = beta[blockIdx.y];
+  } else {
+    st.src = src + off;
+  }
+  // level 0: rows 0 and N
+#pragma unroll 1
+  for (int q = 0; q < 2; ++q) syn_feed<T, UPD, J, 1>(st, st.input());
+  syn_flush<T, UPD, J, 1>(st);
+}
+
+template <typename T, bool UPD, int J>
+hipError_t launch_syn_stream_j(hipStream_t s, const T* src, T* dst, T* p, const T* z,
+                               const double* beta, const int* order, int64_t slab, int nrhs) {
+  const dim3 grid((unsigned)((slab + kStreamBlock - 1) / kStreamBlock), nrhs);
+  wavelet_syn_stream_kernel<T, UPD, J><<<grid, kStreamBlock, 0, s>>>(src, dst, p, z, beta, order,
+                                                                     slab);
+  return hipGetLastError();
+}
+
 template <typename T, bool DOT, int J>
 hipError_t launch_ana_stream_j(hipStream_t s, T* X, const T* p, double* partials, int64_t slab,
                                int nrhs, int* nblk) {
@@ -198,6 +347,56 @@ hipError_t wavelet_ana_stream(hipStream_t s, T* X, const T* p, double* partials,
 
 int wavelet_stream_blocks(int64_t slab) { return (int)((slab + kStreamBlock - 1) / kStreamBlock); }
 
+template <typename T, bool UPD>
+hipError_t wavelet_syn_stream(hipStream_t s, const T* src, T* dst, T* p, const T* z,
+                              const double* beta, const int* order, int J, int64_t slab,
+                              int nrhs) {
+  switch (J) {
+#define STP_J(j) \
+  case j: return launch_syn_stream_j<T, UPD, j>(s, src, dst, p, z, beta, order, slab, nrhs);
+    STP_J(0) STP_J(1) STP_J(2) STP_J(3) STP_J(4) STP_J(5) STP_J(6) STP_J(7)
+    STP_J(8) STP_J(9) STP_J(10) STP_J(11) STP_J(12) STP_J(13) STP_J(14)
+#undef STP_J
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// The rows in the order the synthesis cascade consumes their coefficients:
+// the kernel's cascade run on row numbers.
+std::vector<int> synthesis_read_order(int J) {
+  const int N = 1 << J;
+  std::vector<int> order, k(J + 2, 0);
+  order.reserve(N + 1);
+  // level l receives its next even row `row`
+  auto feed = [&](auto&& self, int l, int row) -> void {
+    if (l > J) return;
+    const int i = k[l]++;
+    if (i == 0) return;
+    const int s = N >> l, m = row - s;
+    order.push_back(m);
+    self(self, l + 1, m - s);
+    self(self, l + 1, m);
+  };
+  order.push_back(0);
+  feed(feed, 1, 0);
+  order.push_back(N);
+  feed(feed, 1, N);
+  for (int l = 1; l <= J; ++l) feed(feed, l + 1, N);
+  return order;
+}
+
+template hipError_t wavelet_syn_stream<double, false>(hipStream_t, const double*, double*, double*,
+                                                      const double*, const double*, const int*,
+                                                      int, int64_t, int);
+template hipError_t wavelet_syn_stream<double, true>(hipStream_t, const double*, double*, double*,
+                                                     const double*, const double*, const int*, int,
+                                                     int64_t, int);
+template hipError_t wavelet_syn_stream<float, false>(hipStream_t, const float*, float*, float*,
+                                                     const float*, const double*, const int*, int,
+                                                     int64_t, int);
+template hipError_t wavelet_syn_stream<float, true>(hipStream_t, const float*, float*, float*,
+                                                    const float*, const double*, const int*, int,
+                                                    int64_t, int);
 template hipError_t wavelet_ana_stream<double, false>(hipStream_t, double*, const double*, double*,
                                                       int, int64_t, int, int*);
 template hipError_t wavelet_ana_stream<double, true>(hipStream_t, double*, const double*, double*,
