@@ -12,8 +12,8 @@
 // level sweep over the column in the same order, so the results are the same
 // value for value; only the interleaving of the levels differs.
 //
-// Rows are read in batches of kStreamBatch per thread, all issued before the
-// first is used.  The level structure is unrolled at compile time (the kernel
+// Rows are read in batches of 8 per thread, all issued before the first is
+// used.  The level structure is unrolled at compile time (the kernel
 // is instantiated per J), so the level states are plain registers.
 //
 // The dot product that PCG needs after the analysis, p^T (W^T y) with y the
@@ -43,7 +43,12 @@ namespace stp {
 namespace {
 
 constexpr int kStreamBlock = 256;
-constexpr int kStreamBatch = 8;
+// rows per batch in both precisions (16 FP32 rows measured slower: the
+// registers cost more occupancy than the deeper batch gains)
+template <typename T>
+constexpr int stream_batch() {
+  return 8;
+}
 
 template <typename T, int J>
 struct AnaState {
@@ -134,24 +139,25 @@ __global__ __launch_bounds__(kStreamBlock) void wavelet_ana_stream_kernel(
     AnaState<T, J> st;
 #pragma unroll
     for (int t = 0; t < J; ++t) st.k[t] = 0;
+    constexpr int B = stream_batch<T>();
 #pragma unroll 1
-    for (int r0 = 0; r0 <= N; r0 += kStreamBatch) {
-      T v[kStreamBatch], w[kStreamBatch];
+    for (int r0 = 0; r0 <= N; r0 += B) {
+      T v[B], w[B];
 #pragma unroll
-      for (int b = 0; b < kStreamBatch; ++b) {
+      for (int b = 0; b < B; ++b) {
         v[b] = r0 + b <= N ? out.x[(int64_t)(r0 + b) * slab] : T(0);
         if constexpr (DOT) w[b] = r0 + b <= N ? xs[(int64_t)(r0 + b) * slab] : T(0);
       }
-      const int nb = min(kStreamBatch, N + 1 - r0);
+      const int nb = min(B, N + 1 - r0);
       if constexpr (DOT) {
 #pragma unroll
-        for (int b = 0; b < kStreamBatch; ++b) acc += (double)w[b] * (double)v[b];  // 0 past N
+        for (int b = 0; b < B; ++b) acc += (double)w[b] * (double)v[b];  // 0 past N
       }
 #pragma unroll 1
       for (int b = 0; b < nb; ++b) {
         const T x = v[0];
 #pragma unroll
-        for (int q = 0; q + 1 < kStreamBatch; ++q) v[q] = v[q + 1];
+        for (int q = 0; q + 1 < B; ++q) v[q] = v[q + 1];
         ana_feed<T, DOT, J, 0>(st, x, out);
       }
     }
@@ -186,8 +192,9 @@ struct SynState {
   T eo[J + 1];  // level l: old value of its current even row
   T ea[J + 1];  // and that value with the contributions of the odd rows seen
   int k[J + 1]; // values received by level l
-  // coefficients in the read order, kStreamBatch at a time
-  T ring[kStreamBatch];
+  // coefficients in the read order, B at a time
+  static constexpr int B = stream_batch<T>();
+  T ring[B];
   int left;     // coefficients in the ring
   int next;     // position in the read order of the next batch
   int orow;     // next output row
@@ -202,10 +209,10 @@ struct SynState {
   __device__ __forceinline__ T input() {
     if (left == 0) {
       constexpr int N = 1 << J;
-      T a[kStreamBatch], b[kStreamBatch];
-      int rows[kStreamBatch];
+      T a[B], b[B];
+      int rows[B];
 #pragma unroll
-      for (int q = 0; q < kStreamBatch; ++q) {
+      for (int q = 0; q < B; ++q) {
         const bool ok = next + q <= N;
         rows[q] = ok ? order[next + q] : 0;
         if constexpr (UPD) {
@@ -216,7 +223,7 @@ struct SynState {
         }
       }
 #pragma unroll
-      for (int q = 0; q < kStreamBatch; ++q) {
+      for (int q = 0; q < B; ++q) {
         if constexpr (UPD) {
           ring[q] = (T)((double)a[q] + beta * (double)b[q]);
           if (next + q <= N) p[(int64_t)rows[q] * slab] = ring[q];
@@ -224,12 +231,12 @@ struct SynState {
           ring[q] = a[q];
         }
       }
-      left = min(kStreamBatch, N + 1 - next);
-      next += kStreamBatch;
+      left = min(B, N + 1 - next);
+      next += B;
     }
     const T x = ring[0];
 #pragma unroll
-    for (int q = 0; q + 1 < kStreamBatch; ++q) ring[q] = ring[q + 1];
+    for (int q = 0; q + 1 < B; ++q) ring[q] = ring[q + 1];
     --left;
     return x;
   }
