@@ -8,8 +8,18 @@
 // (1, 0, 1), (0, 1, 1)), the sums of the element matrices of the 24
 // tetrahedra around a node.
 //
+// Slab layout: line (j, k) of level l occupies 2^l slots; from level 2 on the
+// line is split by i mod 4 into four segments of Q = 2^(l-2) slots, node
+// i = 4q + r at slot r Q + q (slot 0, i = 0, is the line's zero pad).  The
+// colours (i + j + k) mod 4 are then segments: a colour launch of the
+// Gauss-Seidel reads and writes one segment of its own line and reads the
+// other colours' segments of its line and the neighbouring lines, instead of
+// every cache line of x and b.  Level 1 (one node) keeps it at slot 0, the pad
+// at slot 1.
+//
 // Kernels run one 64-lane wave per grid line (j, k) and time row (a
-// grid-stride loop over the rows).  Neighbour values come straight from
+// grid-stride loop over the rows); the Gauss-Seidel launches put 64 / Q lines
+// in one wave on levels below 8, one lane per node of the colour.  Neighbour values come straight from
 // global memory, which the L2 caches; there is no LDS tiling as in the
 // two-dimensional kernels.
 //
@@ -39,15 +49,28 @@ constexpr int kMaxGridRows = 65535;
 // lanes only check i against the grid.
 constexpr int kLane = 64;
 
+// slot of node i (1..n) within its line on level l, the pad's slot, and the
+// node at a slot (0 or n + 1 for the pad)
+__device__ __forceinline__ int pos3(int i, int l) {
+  return l >= 2 ? (i & 3) * (1 << (l - 2)) + (i >> 2) : i - 1;
+}
+__device__ __forceinline__ int pad3(int l) { return l >= 2 ? 0 : 1; }
+__device__ __forceinline__ int node_at3(int p, int l) {
+  if (l < 2) return p + 1;
+  const int q = p & ((1 << (l - 2)) - 1);
+  return 4 * q + (p >> (l - 2));
+}
+
 struct Line3 {
-  int j, k, n, pitch;
-  int64_t off;  // slab offset of node (1, j, k)
+  int j, k, n, pitch, l;
+  int64_t off;  // slab offset of the line
 };
 
 __device__ __forceinline__ Line3 line3(int line, int l) {
   Line3 L;
   L.n = grid_n(l);
   L.pitch = line_pitch(l);
+  L.l = l;
   L.j = line % L.n + 1;
   L.k = line / L.n + 1;
   L.off = (int64_t)line * L.pitch;
@@ -59,7 +82,7 @@ template <typename T, int DI, int DJ, int DK>
 __device__ __forceinline__ T nb3(const T* s, const Line3& L, int i) {
   const int ii = i + DI, jj = L.j + DJ, kk = L.k + DK;
   if (ii < 1 || ii > L.n || jj < 1 || jj > L.n || kk < 1 || kk > L.n) return T(0);
-  return s[L.off + ((int64_t)DK * L.n + DJ) * L.pitch + (ii - 1)];
+  return s[L.off + ((int64_t)DK * L.n + DJ) * L.pitch + pos3(ii, L.l)];
 }
 
 // Stencil weights of C = a A_x + sigma M_x on level l: centre, the six axis
@@ -111,11 +134,15 @@ inline dim3 grid3(int l, int rows) {
 #define FOR_LINE_ROWS(l, rows)                    \
   const Line3 L = line3(blockIdx.x, l);            \
   for (int row = blockIdx.y; row < (rows); row += gridDim.y)
+// lanes over the slots of the line; i: the slot's node, skipped at the pad
+#define FOR_NODES(L)                                                   \
+  for (int p = threadIdx.x; p < (L).pitch; p += kLane)                 \
+    if (const int i = node_at3(p, (L).l); i >= 1 && i <= (L).n)
 
-// writes the pads of a line (the element i = 2^l) and of the slab tail zero
+// writes the pad of a line and the slab tail zero
 template <typename T>
 __device__ __forceinline__ void zero_pads(T* slab_base, const Line3& L, int l, int line) {
-  if (threadIdx.x == 0) slab_base[L.off + L.n] = T(0);
+  if (threadIdx.x == 0) slab_base[L.off + pad3(l)] = T(0);
   const int64_t used = (int64_t)L.n * L.n * L.pitch;
   if (line == L.n * L.n - 1)
     for (int64_t e = used + threadIdx.x; e < slab3_elems(l); e += kLane) slab_base[e] = T(0);
@@ -128,7 +155,7 @@ __global__ __launch_bounds__(kLane) void pack3_kernel(const double* __restrict__
   FOR_LINE_ROWS(K, rows) {
     T* d = dst + row * slab3_elems(K);
     const double* sr = src + row * nx + (int64_t)blockIdx.x * L.n;
-    for (int i = 1 + threadIdx.x; i <= L.n; i += kLane) d[L.off + i - 1] = (T)sr[i - 1];
+    FOR_NODES(L) d[L.off + p] = (T)sr[i - 1];
     zero_pads(d, L, K, blockIdx.x);
   }
 }
@@ -141,7 +168,7 @@ __global__ __launch_bounds__(kLane) void unpack3_kernel(const T* __restrict__ sr
   FOR_LINE_ROWS(K, rows) {
     const T* s = src + row * slab3_elems(K);
     double* dr = dst + row * nx + (int64_t)blockIdx.x * L.n;
-    for (int i = 1 + threadIdx.x; i <= L.n; i += kLane) dr[i - 1] = (double)s[L.off + i - 1];
+    FOR_NODES(L) dr[i - 1] = (double)s[L.off + p];
   }
 }
 
@@ -154,7 +181,7 @@ __global__ __launch_bounds__(kLane) void apply3_kernel(const T* __restrict__ x,
   FOR_LINE_ROWS(K, rows) {
     const T* xr = x + row * slab3_elems(K);
     T* yr = y + row * slab3_elems(K);
-    for (int i = 1 + threadIdx.x; i <= L.n; i += kLane) yr[L.off + i - 1] = mass3(xr, L, i, c);
+    FOR_NODES(L) yr[L.off + p] = mass3(xr, L, i, c);
     zero_pads(yr, L, K, blockIdx.x);
   }
 }
@@ -205,7 +232,7 @@ __global__ __launch_bounds__(kLane) void time_pair3_kernel(const T* __restrict__
     const T* x0 = X + (int64_t)row * slab;
     const T* xm = ti > 0 ? x0 - slab : nullptr;
     const T* xp = ti < N ? x0 + slab : nullptr;
-    for (int i = 1 + threadIdx.x; i <= L.n; i += kLane) {
+    FOR_NODES(L) {
       T o1 = T(0), o2 = T(0);
       auto add = [&](auto nbf, T wm, T wa) {
         const TC3<T> t = tc_of(xm ? nbf(xm) : T(0), nbf(x0), xp ? nbf(xp) : T(0), ti, N);
@@ -234,8 +261,8 @@ __global__ __launch_bounds__(kLane) void time_pair3_kernel(const T* __restrict__
       add(STP_NB(1, 1, 1), T(cm.bd), T(0));
       add(STP_NB(-1, -1, -1), T(cm.bd), T(0));
 #undef STP_NB
-      y1[(int64_t)row * slab + L.off + i - 1] = o1;
-      y2[(int64_t)row * slab + L.off + i - 1] = o2;
+      y1[(int64_t)row * slab + L.off + p] = o1;
+      y2[(int64_t)row * slab + L.off + p] = o2;
     }
     zero_pads(y1 + (int64_t)row * slab, L, K, blockIdx.x);
     zero_pads(y2 + (int64_t)row * slab, L, K, blockIdx.x);
@@ -258,31 +285,38 @@ __global__ __launch_bounds__(kLane) void combine3_kernel(const T* __restrict__ z
     const T* a2 = z2 + (int64_t)row * slab;
     const T* e = (ti == 0 && extra) ? extra + (int64_t)rhs * extra_stride : nullptr;
     T* o = out + (int64_t)row * slab;
-    for (int i = 1 + threadIdx.x; i <= L.n; i += kLane) {
+    FOR_NODES(L) {
       T v = mass3(a1, L, i, cm) + (T(ca.c0) * nb3<T, 0, 0, 0>(a2, L, i) + off3<T, false>(a2, L, i, ca));
       if (e) v += mass3(e, L, i, cm);
-      o[L.off + i - 1] = v;
+      o[L.off + p] = v;
     }
     zero_pads(o, L, K, blockIdx.x);
   }
 }
 
-// One colour of Gauss-Seidel on level l for C = a A + sigma_row M: lanes
-// take the nodes of the line with (i + j + k) mod 4 == colour.
+// One colour of Gauss-Seidel on level l >= 2 for C = a A + sigma_row M.  A
+// wave takes 64 / Q lines (Q = 2^(l-2) slots per segment, at most 64) and
+// one lane per slot of each line's colour segment: line (j, k) holds colour
+// c in segment r = (c - j - k) mod 4, node i = 4q + r.
 template <typename T, bool DIAG>
 __global__ __launch_bounds__(kLane) void relax3_kernel(T* __restrict__ x,
                                                        const T* __restrict__ b, int l, int rows,
                                                        double a, const double* __restrict__ sigma,
                                                        int colour) {
-  FOR_LINE_ROWS(l, rows) {
+  const int n = grid_n(l), Q = 1 << (l - 2);
+  const int line = blockIdx.x * (kLane / Q) + threadIdx.x / Q;
+  const int q = threadIdx.x & (Q - 1);
+  if (line >= n * n) return;
+  const Line3 L = line3(line, l);
+  const int r = (colour - L.j - L.k) & 3;
+  const int i = 4 * q + r;
+  if (i < 1 || i > n) return;
+  const int64_t at = L.off + r * Q + q;
+  for (int row = blockIdx.y; row < rows; row += gridDim.y) {
     const C3 c = coef3(a, sigma ? sigma[row] : 0.0, l);
-    const T inv = T(1.0 / c.c0);
     T* xr = x + row * slab3_elems(l);
     const T* br = b + row * slab3_elems(l);
-    int i0 = ((colour - L.j - L.k) % 4 + 4) % 4;
-    if (i0 == 0) i0 = 4;
-    for (int i = i0 + 4 * threadIdx.x; i <= L.n; i += 4 * kLane)
-      xr[L.off + i - 1] = (br[L.off + i - 1] - off3<T, DIAG>(xr, L, i, c)) * inv;
+    xr[at] = (br[at] - off3<T, DIAG>(xr, L, i, c)) * T(1.0 / c.c0);
   }
 }
 
@@ -297,9 +331,9 @@ __global__ __launch_bounds__(kLane) void residual3_kernel(const T* __restrict__ 
     const T* xr = x + row * slab3_elems(l);
     const T* br = b + row * slab3_elems(l);
     T* rr = r + row * slab3_elems(l);
-    for (int i = 1 + threadIdx.x; i <= L.n; i += kLane)
-      rr[L.off + i - 1] = br[L.off + i - 1] - (T(c.c0) * nb3<T, 0, 0, 0>(xr, L, i) +
-                                                off3<T, DIAG>(xr, L, i, c));
+    FOR_NODES(L)
+      rr[L.off + p] = br[L.off + p] - (T(c.c0) * nb3<T, 0, 0, 0>(xr, L, i) +
+                                       off3<T, DIAG>(xr, L, i, c));
   }
 }
 
@@ -314,15 +348,16 @@ __global__ __launch_bounds__(kLane) void restrict3_kernel(const T* __restrict__ 
     Line3 Lf;
     Lf.n = grid_n(l);
     Lf.pitch = line_pitch(l);
+    Lf.l = l;
     Lf.j = 2 * L.j;
     Lf.k = 2 * L.k;
     Lf.off = ((int64_t)(Lf.k - 1) * Lf.n + (Lf.j - 1)) * Lf.pitch;
     const T* rr = r + row * slab3_elems(l);
     T* o = bc + row * slab3_elems(lc);
-    for (int I = 1 + threadIdx.x; I <= L.n; I += kLane) {
-      const int i = 2 * I;
-      const T half = (axis_sum(rr, Lf, i) + face_sum(rr, Lf, i)) + body_sum(rr, Lf, i);
-      o[L.off + I - 1] = nb3<T, 0, 0, 0>(rr, Lf, i) + T(0.5) * half;
+    FOR_NODES(L) {
+      const int f = 2 * i;  // the fine node under coarse node i
+      const T half = (axis_sum(rr, Lf, f) + face_sum(rr, Lf, f)) + body_sum(rr, Lf, f);
+      o[L.off + p] = nb3<T, 0, 0, 0>(rr, Lf, f) + T(0.5) * half;
     }
     zero_pads(o, L, lc, blockIdx.x);
   }
@@ -334,20 +369,20 @@ template <typename T>
 __global__ __launch_bounds__(kLane) void prolong_add3_kernel(const T* __restrict__ e,
                                                              T* __restrict__ x, int l, int rows) {
   FOR_LINE_ROWS(l, rows) {
-    const int nc = grid_n(l - 1), pc = line_pitch(l - 1);
+    const int nc = grid_n(l - 1), pc = line_pitch(l - 1), lc = l - 1;
     const T* ee = e + row * slab3_elems(l - 1);
     T* xr = x + row * slab3_elems(l);
     const int bb = L.j & 1, cc = L.k & 1, J = L.j >> 1, Kc = L.k >> 1;
     auto at = [&](int I, int Jn, int Kn) -> T {
       return (I >= 1 && I <= nc && Jn >= 1 && Jn <= nc && Kn >= 1 && Kn <= nc)
-                 ? ee[((int64_t)(Kn - 1) * nc + (Jn - 1)) * pc + (I - 1)]
+                 ? ee[((int64_t)(Kn - 1) * nc + (Jn - 1)) * pc + pos3(I, lc)]
                  : T(0);
     };
-    for (int i = 1 + threadIdx.x; i <= L.n; i += kLane) {
+    FOR_NODES(L) {
       const int aa = i & 1, I = i >> 1;
       T v = at(I, J, Kc);
       if (aa | bb | cc) v = T(0.5) * (v + at(I + aa, J + bb, Kc + cc));
-      xr[L.off + i - 1] += v;
+      xr[L.off + p] += v;
     }
   }
 }
@@ -417,11 +452,14 @@ template <typename T>
 hipError_t vcycle3(hipStream_t s, const Mg3Work<T>& w, T* x, const T* b, int l, int rows,
                    double a, const double* sigma) {
   const dim3 g = grid3(l, rows);
+  // Gauss-Seidel launches: 64 / Q lines per wave (l >= 2; l is at least 2 here)
+  const int n = grid_n(l), per = kLane / (1 << (l - 2));
+  const dim3 gr((unsigned)((n * n + per - 1) / per), (unsigned)std::min(rows, kMaxGridRows));
   auto relax = [&](int c) {
     if (sigma)
-      relax3_kernel<T, true><<<g, kLane, 0, s>>>(x, b, l, rows, a, sigma, c);
+      relax3_kernel<T, true><<<gr, kLane, 0, s>>>(x, b, l, rows, a, sigma, c);
     else
-      relax3_kernel<T, false><<<g, kLane, 0, s>>>(x, b, l, rows, a, sigma, c);
+      relax3_kernel<T, false><<<gr, kLane, 0, s>>>(x, b, l, rows, a, sigma, c);
   };
   for (int sw = 0; sw < 3; ++sw)
     for (int c = 0; c < 4; ++c) relax(c);
