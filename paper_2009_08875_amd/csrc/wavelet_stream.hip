@@ -1,6 +1,6 @@
 // The wavelet transforms along time in one pass over the rows (gfx950).
 //
-// One thread per slab column.  The analysis W^T (Section 3.3, eq. (10), fine
+// One thread per slab column (two adjacent columns in FP32).  The analysis W^T (Section 3.3, eq. (10), fine
 // to coarse) is a cascade of per-level lifting steps: level l consumes the
 // values of its rows (multiples of s = N / 2^l) in increasing row order, and
 // every second value it consumes completes one of its odd rows (written out:
@@ -50,25 +50,58 @@ constexpr int stream_batch() {
   return 8;
 }
 
+// What a thread carries: one FP64 column, or two adjacent FP32 columns, so
+// that every load and store moves 8 bytes per lane in both precisions.  The
+// two FP32 columns go through the same operations, component by component.
+typedef float F2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct Lane {
+  using V = T;
+  static constexpr int W = 1;
+  static __device__ __forceinline__ V zero() { return T(0); }
+  // p = z + beta p, in FP64 and rounded to T
+  static __device__ __forceinline__ V upd(V z, V p, double beta) {
+    return (T)((double)z + beta * (double)p);
+  }
+  static __device__ __forceinline__ double dot(V x, V y) { return (double)x * (double)y; }
+};
+template <>
+struct Lane<float> {
+  using V = F2;
+  static constexpr int W = 2;
+  static __device__ __forceinline__ V zero() { return V{0.0f, 0.0f}; }
+  static __device__ __forceinline__ V upd(V z, V p, double beta) {
+    return V{(float)((double)z.x + beta * (double)p.x), (float)((double)z.y + beta * (double)p.y)};
+  }
+  static __device__ __forceinline__ double dot(V a, V b) {
+    return (double)a.x * (double)b.x + (double)a.y * (double)b.y;
+  }
+};
+
 template <typename T, int J>
 struct AnaState {
-  T eo[J];  // old value of the level's current even row
-  T ea[J];  // its value with the contributions of the odd rows seen so far
-  T yo[J];  // the pending odd row
+  using V = typename Lane<T>::V;
+  V eo[J];  // old value of the level's current even row
+  V ea[J];  // its value with the contributions of the odd rows seen so far
+  V yo[J];  // the pending odd row
   int k[J]; // values consumed by the level
 };
 
 // Writes the final value v of row r.
 template <typename T, bool DOT>
 struct AnaOut {
-  T* x;
-  int64_t slab;
-  __device__ __forceinline__ void operator()(int r, T v) { x[(int64_t)r * slab] = v; }
+  using V = typename Lane<T>::V;
+  V* x;
+  int64_t slab;  // row stride in units of V
+  __device__ __forceinline__ void operator()(int r, V v) { x[(int64_t)r * slab] = v; }
 };
 
 // Level J - t consumes value x (its k-th, row k s).
 template <typename T, bool DOT, int J, int t>
-__device__ __forceinline__ void ana_feed(AnaState<T, J>& st, T x, AnaOut<T, DOT>& out) {
+__device__ __forceinline__ void ana_feed(AnaState<T, J>& st, typename Lane<T>::V x,
+                                         AnaOut<T, DOT>& out) {
+  using V = typename Lane<T>::V;
   constexpr int l = J - t;
   constexpr int N = 1 << J;
   constexpr int s = 1 << t;
@@ -85,11 +118,11 @@ __device__ __forceinline__ void ana_feed(AnaState<T, J>& st, T x, AnaOut<T, DOT>
   }
   // x is the old value of the even row i s; the odd row (i - 1) s is final
   const T c = (T)exp2(0.5 * (double)l);
-  const T yo = st.yo[t];
+  const V yo = st.yo[t];
   const T wl = i == 2 ? T(1) : T(0.5);     // boundary weights of rows 0 and N
   const T wr = i == last ? T(1) : T(0.5);
   out((i - 1) * s, c * ((yo - wl * st.eo[t]) - wr * x));
-  const T e = st.ea[t] + T(0.5) * yo;      // the even row (i - 2) s, done at this level
+  const V e = st.ea[t] + T(0.5) * yo;      // the even row (i - 2) s, done at this level
   st.eo[t] = x;
   st.ea[t] = x + T(0.5) * yo;
   if constexpr (l == 1) {
@@ -127,35 +160,38 @@ __device__ double stream_block_sum(double v) {
 template <typename T, bool DOT, int J>
 __global__ __launch_bounds__(kStreamBlock) void wavelet_ana_stream_kernel(
     T* __restrict__ Y, const T* __restrict__ Xs, double* __restrict__ partials, int64_t slab) {
+  using L = Lane<T>;
+  using V = typename L::V;
   constexpr int N = 1 << J;
+  const int64_t vslab = slab / L::W;  // row stride in units of V
   const int64_t col = (int64_t)blockIdx.x * kStreamBlock + threadIdx.x;
   double acc = 0.0;
-  if (col < slab) {
-    const int64_t off = (int64_t)blockIdx.y * (N + 1) * slab + col;
+  if (col < vslab) {
+    const int64_t off = (int64_t)blockIdx.y * (N + 1) * vslab + col;
     AnaOut<T, DOT> out;
-    out.x = Y + off;
-    out.slab = slab;
-    const T* xs = DOT ? Xs + off : nullptr;
+    out.x = reinterpret_cast<V*>(Y) + off;
+    out.slab = vslab;
+    const V* xs = DOT ? reinterpret_cast<const V*>(Xs) + off : nullptr;
     AnaState<T, J> st;
 #pragma unroll
     for (int t = 0; t < J; ++t) st.k[t] = 0;
     constexpr int B = stream_batch<T>();
 #pragma unroll 1
     for (int r0 = 0; r0 <= N; r0 += B) {
-      T v[B], w[B];
+      V v[B], w[B];
 #pragma unroll
       for (int b = 0; b < B; ++b) {
-        v[b] = r0 + b <= N ? out.x[(int64_t)(r0 + b) * slab] : T(0);
-        if constexpr (DOT) w[b] = r0 + b <= N ? xs[(int64_t)(r0 + b) * slab] : T(0);
+        v[b] = r0 + b <= N ? out.x[(int64_t)(r0 + b) * vslab] : L::zero();
+        if constexpr (DOT) w[b] = r0 + b <= N ? xs[(int64_t)(r0 + b) * vslab] : L::zero();
       }
       const int nb = min(B, N + 1 - r0);
       if constexpr (DOT) {
 #pragma unroll
-        for (int b = 0; b < B; ++b) acc += (double)w[b] * (double)v[b];  // 0 past N
+        for (int b = 0; b < B; ++b) acc += L::dot(w[b], v[b]);  // 0 past N
       }
 #pragma unroll 1
       for (int b = 0; b < nb; ++b) {
-        const T x = v[0];
+        const V x = v[0];
 #pragma unroll
         for (int q = 0; q + 1 < B; ++q) v[q] = v[q + 1];
         ana_feed<T, DOT, J, 0>(st, x, out);
@@ -189,43 +225,45 @@ __global__ __launch_bounds__(kStreamBlock) void dot_rows2_kernel(const T* __rest
 
 template <typename T, bool UPD, int J>
 struct SynState {
-  T eo[J + 1];  // level l: old value of its current even row
-  T ea[J + 1];  // and that value with the contributions of the odd rows seen
+  using L = Lane<T>;
+  using V = typename L::V;
+  V eo[J + 1];  // level l: old value of its current even row
+  V ea[J + 1];  // and that value with the contributions of the odd rows seen
   int k[J + 1]; // values received by level l
   // coefficients in the read order, B at a time
   static constexpr int B = stream_batch<T>();
-  T ring[B];
+  V ring[B];
   int left;     // coefficients in the ring
   int next;     // position in the read order of the next batch
   int orow;     // next output row
   const int* order;
-  const T* src;
-  T* p;
-  const T* z;
+  const V* src;
+  V* p;
+  const V* z;
   double beta;
-  T* dst;
-  int64_t slab;
+  V* dst;
+  int64_t slab;  // row stride in units of V
 
-  __device__ __forceinline__ T input() {
+  __device__ __forceinline__ V input() {
     if (left == 0) {
       constexpr int N = 1 << J;
-      T a[B], b[B];
+      V a[B], b[B];
       int rows[B];
 #pragma unroll
       for (int q = 0; q < B; ++q) {
         const bool ok = next + q <= N;
         rows[q] = ok ? order[next + q] : 0;
         if constexpr (UPD) {
-          a[q] = ok ? z[(int64_t)rows[q] * slab] : T(0);
-          b[q] = ok ? p[(int64_t)rows[q] * slab] : T(0);
+          a[q] = ok ? z[(int64_t)rows[q] * slab] : L::zero();
+          b[q] = ok ? p[(int64_t)rows[q] * slab] : L::zero();
         } else {
-          a[q] = ok ? src[(int64_t)rows[q] * slab] : T(0);
+          a[q] = ok ? src[(int64_t)rows[q] * slab] : L::zero();
         }
       }
 #pragma unroll
       for (int q = 0; q < B; ++q) {
         if constexpr (UPD) {
-          ring[q] = (T)((double)a[q] + beta * (double)b[q]);
+          ring[q] = L::upd(a[q], b[q], beta);
           if (next + q <= N) p[(int64_t)rows[q] * slab] = ring[q];
         } else {
           ring[q] = a[q];
@@ -234,18 +272,19 @@ struct SynState {
       left = min(B, N + 1 - next);
       next += B;
     }
-    const T x = ring[0];
+    const V x = ring[0];
 #pragma unroll
     for (int q = 0; q + 1 < B; ++q) ring[q] = ring[q + 1];
     --left;
     return x;
   }
-  __device__ __forceinline__ void output(T v) { dst[(int64_t)(orow++) * slab] = v; }
+  __device__ __forceinline__ void output(V v) { dst[(int64_t)(orow++) * slab] = v; }
 };
 
 // Level l receives x, the value of its k-th even row (row 2 k s, s = N / 2^l).
 template <typename T, bool UPD, int J, int l>
-__device__ __forceinline__ void syn_feed(SynState<T, UPD, J>& st, T x) {
+__device__ __forceinline__ void syn_feed(SynState<T, UPD, J>& st, typename Lane<T>::V x) {
+  using V = typename Lane<T>::V;
   if constexpr (l > J) {
     st.output(x);
   } else {
@@ -260,13 +299,13 @@ __device__ __forceinline__ void syn_feed(SynState<T, UPD, J>& st, T x) {
     // x is the old value of the even row m + s; the odd row m comes in now
     const int m = (2 * i - 1) * s;
     const T c = (T)exp2(0.5 * (double)l);
-    const T d = st.input();
+    const V d = st.input();
     const T wl = m - s == 0 ? T(1) : T(0.5);  // boundary weights of rows 0 and N
     const T wr = m + s == N ? T(1) : T(0.5);
-    const T odd = T(0.5) * (st.eo[l] + x) + c * d;
-    const T even = st.ea[l] - c * wl * d;      // row m - s, done at this level
+    const V odd = T(0.5) * (st.eo[l] + x) + c * d;
+    const V even = st.ea[l] - (c * wl) * d;    // row m - s, done at this level
     st.eo[l] = x;
-    st.ea[l] = x - c * wr * d;
+    st.ea[l] = x - (c * wr) * d;
 #pragma unroll 1
     for (int q = 0; q < 2; ++q) syn_feed<T, UPD, J, l + 1>(st, q == 0 ? even : odd);
   }
@@ -287,10 +326,12 @@ template <typename T, bool UPD, int J>
 __global__ __launch_bounds__(kStreamBlock) void wavelet_syn_stream_kernel(
     const T* src, T* dst, T* p, const T* __restrict__ z, const double* __restrict__ beta,
     const int* __restrict__ order, int64_t slab) {
+  using V = typename Lane<T>::V;
   constexpr int N = 1 << J;
+  const int64_t vslab = slab / Lane<T>::W;  // row stride in units of V
   const int64_t col = (int64_t)blockIdx.x * kStreamBlock + threadIdx.x;
-  if (col >= slab) return;
-  const int64_t off = (int64_t)blockIdx.y * (N + 1) * slab + col;
+  if (col >= vslab) return;
+  const int64_t off = (int64_t)blockIdx.y * (N + 1) * vslab + col;
   SynState<T, UPD, J> st;
 #pragma unroll
   for (int l = 0; l <= J; ++l) st.k[l] = 0;
@@ -298,14 +339,14 @@ __global__ __launch_bounds__(kStreamBlock) void wavelet_syn_stream_kernel(
   st.next = 0;
   st.orow = 0;
   st.order = order;
-  st.slab = slab;
-  st.dst = dst + off;
+  st.slab = vslab;
+  st.dst = reinterpret_cast<V*>(dst) + off;
   if constexpr (UPD) {
-    st.p = p + off;
-    st.z = z + off;
+    st.p = reinterpret_cast<V*>(p) + off;
+    st.z = reinterpret_cast<const V*>(z) + off;
     st.beta = beta[blockIdx.y];
   } else {
-    st.src = src + off;
+    st.src = reinterpret_cast<const V*>(src) + off;
   }
   // level 0: rows 0 and N
 #pragma unroll 1
@@ -316,7 +357,8 @@ __global__ __launch_bounds__(kStreamBlock) void wavelet_syn_stream_kernel(
 template <typename T, bool UPD, int J>
 hipError_t launch_syn_stream_j(hipStream_t s, const T* src, T* dst, T* p, const T* z,
                                const double* beta, const int* order, int64_t slab, int nrhs) {
-  const dim3 grid((unsigned)((slab + kStreamBlock - 1) / kStreamBlock), nrhs);
+  const int64_t threads = slab / Lane<T>::W;
+  const dim3 grid((unsigned)((threads + kStreamBlock - 1) / kStreamBlock), nrhs);
   wavelet_syn_stream_kernel<T, UPD, J><<<grid, kStreamBlock, 0, s>>>(src, dst, p, z, beta, order,
                                                                      slab);
   return hipGetLastError();
@@ -325,7 +367,8 @@ hipError_t launch_syn_stream_j(hipStream_t s, const T* src, T* dst, T* p, const 
 template <typename T, bool DOT, int J>
 hipError_t launch_ana_stream_j(hipStream_t s, T* X, const T* p, double* partials, int64_t slab,
                                int nrhs, int* nblk) {
-  const dim3 grid((unsigned)((slab + kStreamBlock - 1) / kStreamBlock), nrhs);
+  const int64_t threads = slab / Lane<T>::W;
+  const dim3 grid((unsigned)((threads + kStreamBlock - 1) / kStreamBlock), nrhs);
   *nblk = (int)grid.x;
   wavelet_ana_stream_kernel<T, DOT, J><<<grid, kStreamBlock, 0, s>>>(X, p, partials, slab);
   return hipGetLastError();
