@@ -73,6 +73,28 @@ def test_operator_extreme_sizes(stp, J, K, opname):
 
 
 @pytest.mark.parametrize("J,K", CASES)
+@pytest.mark.parametrize("opname", ["W", "WT"])
+def test_fp32_wavelets_extreme_sizes(stp, J, K, opname):
+    """The FP32 transforms (two columns per thread) on the same sizes, against
+    the oracle's FP64 columns: FP32 operator bound."""
+    say(f"extreme size J={J} K={K}: FP32 {opname}")
+    P = Problem(J, K)
+    X = synth.random_field(P.shape, 92)
+    out = np.zeros(X.size)
+    ctx = stp.stp_create(J, K, 1, stp.STP_MIXED)
+    try:
+        stp.stp_apply(ctx, getattr(stp, "STP_OP_" + opname), stp.STP_MIXED, 0, X.reshape(-1), out)
+    finally:
+        stp.stp_destroy(ctx)
+    nodes = _nodes(P.n)
+    fn = orow.W_columns if opname == "W" else orow.WT_columns
+    ref, got = fn(P, X, nodes), out.reshape(P.N + 1, -1)[:, nodes]
+    err = float(np.abs(got - ref).max() / np.abs(ref).max())
+    say(f"  max rel error {err:.2e} (bound 2.0e-4)")
+    assert err <= 2e-4
+
+
+@pytest.mark.parametrize("J,K", CASES)
 @pytest.mark.parametrize("prec", ["FP64", "MIXED"])
 def test_solve_extreme_sizes(stp, J, K, prec):
     say(f"extreme size J={J} K={K}: solve {prec}")
