@@ -1,16 +1,16 @@
 // The wavelet transforms along time in one pass over the rows (gfx950).
 //
-// One thread per slab column (two adjacent columns in FP32).  The analysis W^T (Section 3.3, eq. (10), fine
-// to coarse) is a cascade of per-level lifting steps: level l consumes the
-// values of its rows (multiples of s = N / 2^l) in increasing row order, and
-// every second value it consumes completes one of its odd rows (written out:
-// final) and one of its even rows, which it passes on to level l - 1 as that
-// level's next value.  Each level keeps three values in registers (the old
-// and the accumulating value of its current even row, the pending odd row),
-// so the input is read once, in row order, and every row is written once,
-// when it becomes final.  Each level performs the operations of a level-by-
-// level sweep over the column in the same order, so the results are the same
-// value for value; only the interleaving of the levels differs.
+// One thread per slab column (two adjacent columns in FP32).  The analysis
+// W^T (Section 3.3, eq. (10), fine to coarse) is a cascade of per-level
+// lifting steps: level l consumes the values of its rows (multiples of
+// s = N / 2^l) in increasing row order, and every second value it consumes
+// completes one of its odd rows (written out: final) and one of its even
+// rows, which it passes on to level l - 1 as that level's next value.  Each
+// level keeps three values in registers (the old and the accumulating value
+// of its current even row, the pending odd row), so the input is read once,
+// in row order, and every row is written once, when it becomes final.  Each
+// level performs the operations of a level-by-level sweep over the column,
+// in the same order; only the interleaving of the levels differs.
 //
 // Rows are read in batches of 8 per thread, all issued before the first is
 // used.  The level structure is unrolled at compile time (the kernel
