@@ -191,3 +191,81 @@ def test_3d_refused_requests(stp):
         with pytest.raises(stp.StpError) as e:
             stp.stp_create(2, 3, 1, stp.STP_FP64, opts)
         assert e.value.status == stp.STP_E_UNSUPPORTED
+
+
+# ---- the benchmark shape: N = 2^8, h = 2^-6 (63^3 nodes, 6.4e7 unknowns), the
+# shape of Table 5's N_t = 257, N_x = 250047 row.  The oracle evaluates the
+# operators on sampled time rows and spatial columns (tests/oracle_rows.py).
+J3B, K3B = 8, 6
+ROWS3B = [0, 1, 128, 255, 256]
+
+
+@pytest.fixture(scope="module")
+def bench3d():
+    from tests import oracle_rows as orow
+
+    P = Problem(J3B, K3B, dim=3)
+    X = np.random.default_rng(3303).standard_normal(P.shape)
+    n3 = P.n ** 3
+    nodes = sorted({0, 1, P.n - 1, n3 // 2, n3 - 1})
+    lev = oracle.wavelet.row_levels(J3B)[ROWS3B].astype(np.float64)
+    Xr = X[ROWS3B]
+    y = space3d.mg_apply(Xr, K3B, P.alpha, 2.0 ** lev, P.cycles, P.sweeps)
+    ref = {
+        "S": orow.S_rows(P, X, ROWS3B),
+        "KSPACE": orow.Kx_rows(P, X, ROWS3B),
+        "KX": space3d.mg_apply(P.A(y), K3B, P.alpha, 2.0 ** lev, P.cycles, P.sweeps),
+        "W": orow.W_columns(P, X, nodes),
+        "WT": orow.WT_columns(P, X, nodes),
+    }
+    amp = 12.0 * np.abs(y).max() / np.abs(P.A(y)).max()
+    return P, X, nodes, ref, amp
+
+
+@pytest.mark.parametrize("prec", ["FP64", "MIXED"])
+def test_operators_3d_bench_shape(stp, bench3d, prec):
+    P, X, nodes, ref, amp = bench3d
+    p = getattr(stp, "STP_" + prec)
+    eps = np.finfo(np.float64 if prec == "FP64" else np.float32).eps / 2
+    ctx = stp.stp_create(J3B, K3B, 1, p, D3)
+    try:
+        for name in ["S", "KSPACE", "KX", "W", "WT"]:
+            out = np.zeros(X.size)
+            stp.stp_apply(ctx, getattr(stp, "STP_OP_" + name), p, 0, flat(X), out)
+            out = out.reshape(P.shape)
+            if name in ("W", "WT"):
+                got = out.reshape(P.N + 1, -1)[:, nodes]
+            else:
+                got = out[ROWS3B]
+            err = _max_rel(got, ref[name])
+            tol = 1e-12 if prec == "FP64" else 2e-4
+            if name == "KX":
+                tol = max(tol, 500 * eps * amp)
+            say(f"3D bench shape {prec} {name}: {err:.2e} (bound {tol:.1e})")
+            assert err <= tol, name
+    finally:
+        stp.stp_destroy(ctx)
+
+
+def test_solves_3d_bench_shape(stp, bench3d):
+    """Section 5.2's 3D test problem at the benchmark shape: FP64 and mixed
+    solves to 1e-8, the sampled residual f - S u of the FP64 solution against
+    the oracle's rows (1e-6 of f), the mixed solution against the FP64 one."""
+    from tests import oracle_rows as orow
+
+    P = bench3d[0]
+    u0 = synth.sine_product_3d(K3B)
+    sol = {}
+    for prec in ("FP64", "MIXED"):
+        status, st, u = _solve(stp, J3B, K3B, getattr(stp, "STP_" + prec), D3, None, u0, 1e-8)
+        say(f"3D bench shape {prec}: status {status}, iterations {st[0]['iterations']}, "
+            f"outer {st[0]['outer_iterations']}")
+        assert status == stp.STP_OK
+        sol[prec] = u[0]
+    f = orow.rhs_rows(P, lambda lo, hi: None, u0, ROWS3B)
+    Su = orow.S_rows(P, sol["FP64"], ROWS3B)
+    res = np.linalg.norm((f - Su).reshape(len(ROWS3B), -1), axis=1).max()
+    scale = np.linalg.norm(f.reshape(len(ROWS3B), -1), axis=1).max()
+    diff = rel_err(sol["MIXED"], sol["FP64"])
+    say(f"3D bench shape: sampled residual / f {res / scale:.2e}, mixed vs FP64 {diff:.2e}")
+    assert res <= 1e-6 * scale and diff <= 1e-6
