@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--workload", default="heat2d_J12_K9", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--nested", type=int, default=0,
+                    help="FP64: nested iteration over this many coarser meshes (Section 4.2); "
+                         "the comparison run is then the same solve without it")
     ap.add_argument("--lookahead", type=int, default=0, choices=[0, -1],
                     help="0: PCG iterations in batches between flag reads; -1: read after each")
     ap.add_argument("--no-compare", action="store_true", help="skip the other-precision run")
@@ -409,7 +412,7 @@ def main():
     J, K, nrhs, seed, u0kind = WORKLOADS[args.workload]
     prec = stp.STP_FP64 if args.precision == "fp64" else stp.STP_MIXED
     dim = 3 if u0kind == "sin3" else 2
-    opts = {"dim": dim, "lookahead": args.lookahead}
+    opts = {"dim": dim, "lookahead": args.lookahead, "nested": args.nested}
     unknowns = (2 ** J + 1) * (2 ** K - 1) ** dim * nrhs
     print(f"# workload {args.workload} J={J} K={K} nrhs={nrhs} precision={args.precision}",
           file=sys.stderr, flush=True)
@@ -449,8 +452,10 @@ def main():
 
     compare = None
     if not args.no_compare:
-        other = stp.STP_MIXED if prec == stp.STP_FP64 else stp.STP_FP64
-        ctx = stp.stp_create(J, K, nrhs, other, opts, stream=torch.cuda.current_stream())
+        # the other precision; with nested iteration, the same precision without it
+        other = prec if args.nested else (stp.STP_MIXED if prec == stp.STP_FP64 else stp.STP_FP64)
+        ctx = stp.stp_create(J, K, nrhs, other, dict(opts, nested=0),
+                             stream=torch.cuda.current_stream())
         load_inputs(stp, ctx, J, K, nrhs, seed, u0kind, torch)
         t2, st2 = run_solves(stp, ctx, nrhs, args.tol, 2, 1, torch)
         u2 = torch.zeros_like(u_main)
@@ -460,6 +465,7 @@ def main():
         stp.stp_destroy(ctx)
         compare = {
             "precision": "mixed" if other == stp.STP_MIXED else "fp64",
+            "nested": 0,
             "time_to_solve_s": round(t2, 4),
             "inner_iterations": st2[-1][0]["iterations"],
             "outer_iterations": st2[-1][0]["outer_iterations"],
@@ -493,6 +499,9 @@ def main():
         "config": {"workload": args.workload, "J": J, "K": K, "nrhs": nrhs, "dim": dim,
                    "unknowns": unknowns, "precision": args.precision, "rel_tol": args.tol,
                    "iterations": its, "time_to_solve_s": round(t_step, 4),
+                   **({"nested": args.nested,
+                       "coarse_iterations": stats[-1][0]["coarse_iterations"]}
+                      if args.nested else {}),
                    "parallelism": "single-gpu"},
         "roofline": roofline,
         "cpu_baseline": cpu,
