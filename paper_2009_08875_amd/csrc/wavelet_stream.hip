@@ -79,13 +79,36 @@ struct Lane<float> {
   }
 };
 
+// The analysis keeps the state of its kAnaRegLevels finest levels in
+// registers; a coarser level acts once per 64 or more input rows, and its
+// state lives in LDS (one slot per thread and value).  With the state of all
+// levels in registers the kernel needed up to 198 VGPRs (two waves per SIMD);
+// this way about 100, and four to five waves per SIMD up to J = 12.
+constexpr int kAnaRegLevels = 6;
+
 template <typename T, int J>
 struct AnaState {
   using V = typename Lane<T>::V;
-  V eo[J];  // old value of the level's current even row
-  V ea[J];  // its value with the contributions of the odd rows seen so far
-  V yo[J];  // the pending odd row
-  int k[J]; // values consumed by the level
+  static constexpr int R = J < kAnaRegLevels ? J : kAnaRegLevels;
+  V reo[R];  // old value of the level's current even row
+  V rea[R];  // its value with the contributions of the odd rows seen so far
+  V ryo[R];  // the pending odd row
+  int k[J];  // values consumed by the level
+  V* lds;    // levels t >= R: lds[(3 (t - R) + q) kStreamBlock + thread], q = eo, ea, yo
+
+  template <int t, int q>
+  __device__ __forceinline__ V& at() {
+    if constexpr (t < R) {
+      if constexpr (q == 0) return reo[t];
+      else if constexpr (q == 1) return rea[t];
+      else return ryo[t];
+    } else {
+      return lds[(3 * (t - R) + q) * kStreamBlock + threadIdx.x];
+    }
+  }
+  template <int t> __device__ __forceinline__ V& eo() { return at<t, 0>(); }
+  template <int t> __device__ __forceinline__ V& ea() { return at<t, 1>(); }
+  template <int t> __device__ __forceinline__ V& yo() { return at<t, 2>(); }
 };
 
 // Writes the final value v of row r.
@@ -108,26 +131,27 @@ __device__ __forceinline__ void ana_feed(AnaState<T, J>& st, typename Lane<T>::V
   constexpr int last = 1 << l;
   const int i = st.k[t]++;
   if (i == 0) {
-    st.eo[t] = x;
-    st.ea[t] = x;
+    st.template eo<t>() = x;
+    st.template ea<t>() = x;
     return;
   }
   if (i & 1) {
-    st.yo[t] = x;
+    st.template yo<t>() = x;
     return;
   }
   // x is the old value of the even row i s; the odd row (i - 1) s is final
   const T c = (T)exp2(0.5 * (double)l);
-  const V yo = st.yo[t];
+  const V yo = st.template yo<t>();
   const T wl = i == 2 ? T(1) : T(0.5);     // boundary weights of rows 0 and N
   const T wr = i == last ? T(1) : T(0.5);
-  out((i - 1) * s, c * ((yo - wl * st.eo[t]) - wr * x));
-  const V e = st.ea[t] + T(0.5) * yo;      // the even row (i - 2) s, done at this level
-  st.eo[t] = x;
-  st.ea[t] = x + T(0.5) * yo;
+  out((i - 1) * s, c * ((yo - wl * st.template eo<t>()) - wr * x));
+  const V e = st.template ea<t>() + T(0.5) * yo;  // the even row (i - 2) s, done at this level
+  const V e2 = x + T(0.5) * yo;
+  st.template eo<t>() = x;
+  st.template ea<t>() = e2;
   if constexpr (l == 1) {
     out(0, e);
-    out(N, st.ea[t]);
+    out(N, e2);
   } else {
     ana_feed<T, DOT, J, t + 1>(st, e, out);
   }
@@ -137,7 +161,7 @@ __device__ __forceinline__ void ana_feed(AnaState<T, J>& st, typename Lane<T>::V
 template <typename T, bool DOT, int J, int t>
 __device__ __forceinline__ void ana_flush(AnaState<T, J>& st, AnaOut<T, DOT>& out) {
   if constexpr (t + 1 < J) {
-    ana_feed<T, DOT, J, t + 1>(st, st.ea[t], out);
+    ana_feed<T, DOT, J, t + 1>(st, st.template ea<t>(), out);
     ana_flush<T, DOT, J, t + 1>(st, out);
   }
 }
@@ -173,6 +197,9 @@ __global__ __launch_bounds__(kStreamBlock) void wavelet_ana_stream_kernel(
     out.slab = vslab;
     const V* xs = DOT ? reinterpret_cast<const V*>(Xs) + off : nullptr;
     AnaState<T, J> st;
+    constexpr int LL = J > AnaState<T, J>::R ? J - AnaState<T, J>::R : 1;
+    __shared__ V lds_state[3 * LL * kStreamBlock];
+    st.lds = lds_state;
 #pragma unroll
     for (int t = 0; t < J; ++t) st.k[t] = 0;
     constexpr int B = stream_batch<T>();
