@@ -6,8 +6,9 @@
 // meets a problem shape, tuned() runs every candidate on the launch's real
 // arguments (the kernels are pure: they read their inputs and overwrite their
 // outputs, so repeating them is harmless), times each with HIP events on the
-// launch stream, and remembers the fastest for that shape for the rest of the
-// process.  While the stream is being captured into a graph nothing can be
+// launch stream in three rounds over all candidates (alternating direction;
+// a candidate's time is its fastest round), and remembers the fastest for that
+// shape for the rest of the process.  While the stream is being captured into a graph nothing can be
 // timed: an unknown shape then gets the fallback candidate, not remembered.
 // STP_TUNE=0 in the environment disables tuning (always the fallback);
 // STP_TUNE_LOG=1 prints each decision to stderr.
