@@ -21,7 +21,8 @@
 // grid-stride loop over the rows); the Gauss-Seidel launches put 64 / Q lines
 // in one wave on levels below 8, one lane per node of the colour.  Neighbour values come straight from
 // global memory, which the L2 caches; there is no LDS tiling as in the
-// two-dimensional kernels.
+// two-dimensional kernels.  Levels 4..1 of a V-cycle run in one launch with one
+// workgroup per time row and every level in LDS (mg3_coarse_kernel).
 //
 // Multigrid (K_x and the K_l of Theorem 3.1, Section 5.1's two V-cycles with
 // three Gauss-Seidel steps per grid): the colours (i + j + k) mod 4 -- the
@@ -404,6 +405,196 @@ __global__ __launch_bounds__(256) void zero3_kernel(T* __restrict__ x, int64_t c
   if (i < count) x[i] = T(0);
 }
 
+// ---- V-cycles on levels L..1 (L <= kCoarse3) of one time row per workgroup,
+// every level in LDS.  Each level is a cube of (n + 2)^3 values with a zero
+// border, node (i, j, k) at (k p + j) p + i, p = n + 2; the schedule and the
+// arithmetic are those of the launches above (relax3_kernel, residual3_kernel,
+// restrict3_kernel, prolong_add3_kernel, coarsest3_kernel), one barrier per
+// colour step instead of one launch.
+constexpr int kCoarse3 = 4;
+constexpr int kCoarse3Threads = 512;
+
+template <int l>
+struct Cube {
+  static constexpr int n = (1 << l) - 1;
+  static constexpr int p = n + 2;
+  static constexpr int size = p * p * p;
+  static constexpr int m = (n + 3) / 4;  // nodes of one colour per grid line, at most
+};
+
+// LDS layout for top level L: x_l then b_l for l = L..1, then level L's residual
+template <int L>
+struct Layout3 {
+  static constexpr int x(int l) {
+    int o = 0;
+    for (int k = L; k > l; --k) o += 2 * ((1 << k) + 1) * ((1 << k) + 1) * ((1 << k) + 1);
+    return o;
+  }
+  static constexpr int b(int l) { return x(l) + ((1 << l) + 1) * ((1 << l) + 1) * ((1 << l) + 1); }
+  static constexpr int r = x(0);
+  static constexpr int total = r + ((1 << L) + 1) * ((1 << L) + 1) * ((1 << L) + 1);
+};
+
+template <int l, int DI, int DJ, int DK, typename T>
+__device__ __forceinline__ T cnb(const T* x, int q) {
+  constexpr int p = Cube<l>::p;
+  return x[q + (DK * p + DJ) * p + DI];
+}
+template <int l, typename T>
+__device__ __forceinline__ T caxis(const T* x, int q) {
+  return ((cnb<l, 1, 0, 0>(x, q) + cnb<l, -1, 0, 0>(x, q)) +
+          (cnb<l, 0, 1, 0>(x, q) + cnb<l, 0, -1, 0>(x, q))) +
+         (cnb<l, 0, 0, 1>(x, q) + cnb<l, 0, 0, -1>(x, q));
+}
+template <int l, typename T>
+__device__ __forceinline__ T cface(const T* x, int q) {
+  return ((cnb<l, 1, 1, 0>(x, q) + cnb<l, -1, -1, 0>(x, q)) +
+          (cnb<l, 1, 0, 1>(x, q) + cnb<l, -1, 0, -1>(x, q))) +
+         (cnb<l, 0, 1, 1>(x, q) + cnb<l, 0, -1, -1>(x, q));
+}
+template <int l, typename T>
+__device__ __forceinline__ T cbody(const T* x, int q) {
+  return cnb<l, 1, 1, 1>(x, q) + cnb<l, -1, -1, -1>(x, q);
+}
+template <int l, bool DIAG, typename T>
+__device__ __forceinline__ T coff(const T* x, int q, const C3& c) {
+  T v = T(c.ax) * caxis<l>(x, q);
+  if constexpr (DIAG) v += T(c.fd) * cface<l>(x, q) + T(c.bd) * cbody<l>(x, q);
+  return v;
+}
+
+template <int l, bool DIAG, typename T>
+__device__ __forceinline__ void crelax(T* x, const T* b, int colour, const C3& c) {
+  constexpr int n = Cube<l>::n, p = Cube<l>::p, m = Cube<l>::m;
+  const T inv = T(1.0 / c.c0);
+  for (int t = threadIdx.x; t < n * n * m; t += kCoarse3Threads) {
+    const int line = t / m, qq = t - line * m;
+    const int j = line % n + 1, k = line / n + 1;
+    const int i = 4 * qq + ((colour - j - k) & 3);
+    if (i < 1 || i > n) continue;
+    const int q = (k * p + j) * p + i;
+    x[q] = (b[q] - coff<l, DIAG>(x, q, c)) * inv;
+  }
+}
+
+template <int l, bool DIAG, typename T>
+__device__ void csweeps(T* x, const T* b, const C3& c, bool forward) {
+  for (int s = 0; s < 3; ++s)
+    for (int k = 0; k < 4; ++k) {
+      crelax<l, DIAG>(x, b, forward ? k : 3 - k, c);
+      __syncthreads();
+    }
+}
+
+template <int L, int l, bool DIAG, typename T>
+__device__ void cvcycle(T* sh, double a, double sg) {
+  T* x = sh + Layout3<L>::x(l);
+  T* bl = sh + Layout3<L>::b(l);
+  if constexpr (l == 1) {
+    if (threadIdx.x == 0) {
+      constexpr int q = (Cube<1>::p + 1) * Cube<1>::p + 1;
+      x[q] = bl[q] / T(coef3(a, sg, 1).c0);
+    }
+    __syncthreads();
+  } else {
+    constexpr int n = Cube<l>::n, p = Cube<l>::p;
+    constexpr int nc = Cube<l - 1>::n, pc = Cube<l - 1>::p;
+    T* r = sh + Layout3<L>::r;
+    {
+      const C3 c = coef3(a, sg, l);
+      csweeps<l, DIAG>(x, bl, c, true);
+      for (int t = threadIdx.x; t < n * n * n; t += kCoarse3Threads) {
+        const int i = t % n + 1, j = (t / n) % n + 1, k = t / (n * n) + 1;
+        const int q = (k * p + j) * p + i;
+        r[q] = bl[q] - (T(c.c0) * x[q] + coff<l, DIAG>(x, q, c));
+      }
+    }
+    __syncthreads();
+    T* bc = sh + Layout3<L>::b(l - 1);
+    T* xc = sh + Layout3<L>::x(l - 1);
+    for (int t = threadIdx.x; t < nc * nc * nc; t += kCoarse3Threads) {
+      const int I = t % nc + 1, J = (t / nc) % nc + 1, K = t / (nc * nc) + 1;
+      const int q = (2 * K * p + 2 * J) * p + 2 * I;
+      const T half = (caxis<l>(r, q) + cface<l>(r, q)) + cbody<l>(r, q);
+      const int qc = (K * pc + J) * pc + I;
+      bc[qc] = r[q] + T(0.5) * half;
+      xc[qc] = T(0);
+    }
+    __syncthreads();
+    cvcycle<L, l - 1, DIAG>(sh, a, sg);
+    for (int t = threadIdx.x; t < n * n * n; t += kCoarse3Threads) {
+      const int i = t % n + 1, j = (t / n) % n + 1, k = t / (n * n) + 1;
+      const int aa = i & 1, bb = j & 1, cc = k & 1;
+      const int q0 = ((k >> 1) * pc + (j >> 1)) * pc + (i >> 1);
+      T v = xc[q0];
+      if (aa | bb | cc) v = T(0.5) * (v + xc[q0 + (cc * pc + bb) * pc + aa]);
+      x[(k * p + j) * p + i] += v;
+    }
+    __syncthreads();
+    csweeps<l, DIAG>(x, bl, coef3(a, sg, l), false);
+  }
+}
+
+// `cycles` V-cycles from xin (NULL: zero) on one time row per workgroup; the
+// result, or A_x applied to it, to xout (the whole slab, pads zero).
+template <typename T, int L, bool DIAG>
+__global__ __launch_bounds__(kCoarse3Threads) void mg3_coarse_kernel(
+    const T* __restrict__ xin, const T* __restrict__ b, T* __restrict__ xout, double a,
+    const double* __restrict__ sigma, int write_Ax, int cycles) {
+  __shared__ T sh[Layout3<L>::total];
+  constexpr int n = Cube<L>::n, p = Cube<L>::p, pitch = 1 << L;
+  for (int t = threadIdx.x; t < Layout3<L>::total; t += kCoarse3Threads) sh[t] = T(0);
+  __syncthreads();
+  const int row = blockIdx.x;
+  const double sg = sigma ? sigma[row] : 0.0;
+  const int64_t base = (int64_t)row * slab3_elems(L);
+  T* x = sh + Layout3<L>::x(L);
+  T* bl = sh + Layout3<L>::b(L);
+  for (int t = threadIdx.x; t < n * n * n; t += kCoarse3Threads) {
+    const int i = t % n + 1, line = t / n;
+    const int64_t g = base + (int64_t)line * pitch + pos3(i, L);
+    const int q = ((line / n + 1) * p + (line % n + 1)) * p + i;
+    bl[q] = b[g];
+    if (xin) x[q] = xin[g];
+  }
+  __syncthreads();
+  for (int c = 0; c < cycles; ++c) cvcycle<L, L, DIAG>(sh, a, sg);
+  const C3 ac = coef3(1.0, 0.0, L);  // A_x itself
+  for (int64_t e = threadIdx.x; e < slab3_elems(L); e += kCoarse3Threads) {
+    const int line = (int)(e / pitch), slot = (int)(e - (int64_t)line * pitch);
+    const int i = node_at3(slot, L);
+    T v = T(0);
+    if (line < n * n && i >= 1 && i <= n) {
+      const int q = ((line / n + 1) * p + (line % n + 1)) * p + i;
+      v = x[q];
+      if (write_Ax)
+        v = (T(ac.c0) * v + T(ac.ax) * caxis<L>(x, q)) +
+            (T(ac.fd) * cface<L>(x, q) + T(ac.bd) * cbody<L>(x, q));
+    }
+    xout[base + e] = v;
+  }
+}
+
+template <typename T, bool DIAG>
+hipError_t launch_coarse3(hipStream_t s, const T* xin, const T* b, T* xout, int L, int rows,
+                          double a, const double* sigma, bool write_Ax, int cycles) {
+  const int wa = write_Ax ? 1 : 0;
+  switch (L) {
+    case 2: mg3_coarse_kernel<T, 2, DIAG><<<rows, kCoarse3Threads, 0, s>>>(xin, b, xout, a, sigma, wa, cycles); break;
+    case 3: mg3_coarse_kernel<T, 3, DIAG><<<rows, kCoarse3Threads, 0, s>>>(xin, b, xout, a, sigma, wa, cycles); break;
+    case 4: mg3_coarse_kernel<T, 4, DIAG><<<rows, kCoarse3Threads, 0, s>>>(xin, b, xout, a, sigma, wa, cycles); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t coarse3(hipStream_t s, const T* xin, const T* b, T* xout, int L, int rows, double a,
+                   const double* sigma, bool write_Ax, int cycles) {
+  return sigma ? launch_coarse3<T, true>(s, xin, b, xout, L, rows, a, sigma, write_Ax, cycles)
+               : launch_coarse3<T, false>(s, xin, b, xout, L, rows, a, sigma, write_Ax, cycles);
+}
+
 }  // namespace
 
 template <typename T>
@@ -468,8 +659,11 @@ hipError_t vcycle3(hipStream_t s, const Mg3Work<T>& w, T* x, const T* b, int l, 
   else
     residual3_kernel<T, false><<<g, kLane, 0, s>>>(x, b, w.r[l], l, rows, a, sigma);
   restrict3_kernel<T><<<grid3(l - 1, rows), kLane, 0, s>>>(w.r[l], w.b[l - 1], l, rows);
-  if (l - 1 == 1) {
-    coarsest3_kernel<T><<<(rows + 63) / 64, 64, 0, s>>>(w.b[1], w.x[1], rows, a, sigma);
+  if (l - 1 <= kCoarse3) {
+    // levels l - 1 .. 1 from zero in one launch, every level in LDS
+    const hipError_t e =
+        coarse3<T>(s, nullptr, w.b[l - 1], w.x[l - 1], l - 1, rows, a, sigma, false, 1);
+    if (e != hipSuccess) return e;
   } else {
     const int64_t cnt = (int64_t)rows * slab3_elems(l - 1);
     zero3_kernel<T><<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(w.x[l - 1], cnt);
@@ -485,6 +679,8 @@ hipError_t vcycle3(hipStream_t s, const Mg3Work<T>& w, T* x, const T* b, int l, 
 template <typename T>
 hipError_t mg3_apply(hipStream_t s, const Mg3Work<T>& w, const T* b, T* x, int K, int rows,
                      double a, const double* sigma, int vcycles, bool write_Ax) {
+  if (K >= 2 && K <= kCoarse3)  // every cycle in one launch, every level in LDS
+    return coarse3<T>(s, nullptr, b, x, K, rows, a, sigma, write_Ax, vcycles);
   T* xk = write_Ax ? w.x[K] : x;
   const int64_t cnt = (int64_t)rows * slab3_elems(K);
   zero3_kernel<T><<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(xk, cnt);
