@@ -187,39 +187,25 @@ __global__ __launch_bounds__(kLane) void apply3_kernel(const T* __restrict__ x,
   }
 }
 
-// The four time combinations of Lemma 4.2 of one node value in rows
-// i - 1, i, i + 1 (exact hat integrals, one-sided at t = 0 and t = 1).
-template <typename T>
-struct TC3 {
-  T At, Mt, L, LT;
+// Weights of the four time combinations of Lemma 4.2 on time rows i - 1, i,
+// i + 1 (exact hat integrals, one-sided at t = 0 and t = 1): A_t, M_t, L and
+// L^T applied to a function of time are w[0] x_{i-1} + w[1] x_i + w[2] x_{i+1}.
+struct TW3 {
+  double At[3], Mt[3], L[3], LT[3];
 };
-template <typename T>
-__device__ __forceinline__ TC3<T> tc_of(T xm, T x0, T xp, int i, int N) {
-  const T inv_tau = T((double)N), tau6 = T(1.0 / (6.0 * (double)N));
-  TC3<T> r;
-  if (i == 0) {
-    r.At = (x0 - xp) * inv_tau;
-    r.Mt = tau6 * (T(2) * x0 + xp);
-    r.L = (xp - x0) / T(2);
-    r.LT = -(x0 + xp) / T(2);
-  } else if (i == N) {
-    r.At = (x0 - xm) * inv_tau;
-    r.Mt = tau6 * (xm + T(2) * x0);
-    r.L = (x0 - xm) / T(2);
-    r.LT = (xm + x0) / T(2);
-  } else {
-    r.At = (T(2) * x0 - xm - xp) * inv_tau;
-    r.Mt = tau6 * ((xm + T(4) * x0) + xp);
-    r.L = (xp - xm) / T(2);
-    r.LT = (xm - xp) / T(2);
-  }
-  return r;
+__device__ __forceinline__ TW3 time_weights3(int i, int N) {
+  const double n = (double)N, m6 = 1.0 / (6.0 * (double)N);
+  if (i == 0) return {{0.0, n, -n}, {0.0, 2.0 * m6, m6}, {0.0, -0.5, 0.5}, {0.0, -0.5, -0.5}};
+  if (i == N) return {{-n, n, 0.0}, {m6, 2.0 * m6, 0.0}, {-0.5, 0.5, 0.0}, {0.5, 0.5, 0.0}};
+  return {{-n, 2.0 * n, -n}, {m6, 4.0 * m6, m6}, {-0.5, 0.0, 0.5}, {0.5, 0.0, -0.5}};
 }
 
 // MODE 0: y1 = M (A_t X) + A (L^T X), y2 = A (M_t X) + M (L X)
 // MODE 1: G1 = M (L^T g), G0 = M (M_t g)
-// Each output node needs the time combinations at its 15 mass neighbours;
-// they are formed from the three time rows on the fly.
+// The time combinations are linear in the three time rows, so each output is
+// a weighted sum of A x and M x of rows i - 1, i, i + 1: a lane forms those
+// spatial products one time row after another (15 loads each) and
+// accumulates them.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kLane) void time_pair3_kernel(const T* __restrict__ X,
                                                            T* __restrict__ y1,
@@ -230,38 +216,26 @@ __global__ __launch_bounds__(kLane) void time_pair3_kernel(const T* __restrict__
   const C3 ca = coef3(1.0, 0.0, K), cm = coef3(0.0, 1.0, K);
   FOR_LINE_ROWS(K, rows) {
     const int rhs = row / (N + 1), ti = row - rhs * (N + 1);
+    const TW3 w = time_weights3(ti, N);
     const T* x0 = X + (int64_t)row * slab;
-    const T* xm = ti > 0 ? x0 - slab : nullptr;
-    const T* xp = ti < N ? x0 + slab : nullptr;
     FOR_NODES(L) {
       T o1 = T(0), o2 = T(0);
-      auto add = [&](auto nbf, T wm, T wa) {
-        const TC3<T> t = tc_of(xm ? nbf(xm) : T(0), nbf(x0), xp ? nbf(xp) : T(0), ti, N);
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        if ((t == 0 && ti == 0) || (t == 2 && ti == N)) continue;
+        const T* xs = x0 + (t - 1) * slab;
+        const T axis = axis_sum(xs, L, i);
+        const T Mx = (T(cm.c0) * nb3<T, 0, 0, 0>(xs, L, i) + T(cm.ax) * axis) +
+                     (T(cm.fd) * face_sum(xs, L, i) + T(cm.bd) * body_sum(xs, L, i));
         if constexpr (MODE == 0) {
-          o1 += wm * t.At + wa * t.LT;
-          o2 += wa * t.Mt + wm * t.L;
+          const T Ax = T(ca.c0) * nb3<T, 0, 0, 0>(xs, L, i) + T(ca.ax) * axis;
+          o1 += T(w.At[t]) * Mx + T(w.LT[t]) * Ax;
+          o2 += T(w.Mt[t]) * Ax + T(w.L[t]) * Mx;
         } else {
-          o1 += wm * t.LT;
-          o2 += wm * t.Mt;
+          o1 += T(w.LT[t]) * Mx;
+          o2 += T(w.Mt[t]) * Mx;
         }
-      };
-#define STP_NB(DI, DJ, DK) [&](const T* s) { return nb3<T, DI, DJ, DK>(s, L, i); }
-      add(STP_NB(0, 0, 0), T(cm.c0), T(ca.c0));
-      add(STP_NB(1, 0, 0), T(cm.ax), T(ca.ax));
-      add(STP_NB(-1, 0, 0), T(cm.ax), T(ca.ax));
-      add(STP_NB(0, 1, 0), T(cm.ax), T(ca.ax));
-      add(STP_NB(0, -1, 0), T(cm.ax), T(ca.ax));
-      add(STP_NB(0, 0, 1), T(cm.ax), T(ca.ax));
-      add(STP_NB(0, 0, -1), T(cm.ax), T(ca.ax));
-      add(STP_NB(1, 1, 0), T(cm.fd), T(0));
-      add(STP_NB(-1, -1, 0), T(cm.fd), T(0));
-      add(STP_NB(1, 0, 1), T(cm.fd), T(0));
-      add(STP_NB(-1, 0, -1), T(cm.fd), T(0));
-      add(STP_NB(0, 1, 1), T(cm.fd), T(0));
-      add(STP_NB(0, -1, -1), T(cm.fd), T(0));
-      add(STP_NB(1, 1, 1), T(cm.bd), T(0));
-      add(STP_NB(-1, -1, -1), T(cm.bd), T(0));
-#undef STP_NB
+      }
       y1[(int64_t)row * slab + L.off + p] = o1;
       y2[(int64_t)row * slab + L.off + p] = o2;
     }
