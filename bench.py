@@ -449,6 +449,11 @@ def main():
         "launches": d["launches"],
         "kernels": table,
     }
+    if dim == 3:
+        # the 3D multigrid runs as many short launches per level and colour,
+        # which the library does not bracket with events
+        roofline["scope"] = ("dominant among the timed launches; the 3D multigrid launches are not "
+                             "timed here and take most of the solve (kernel trace)")
 
     compare = None
     if not args.no_compare:
