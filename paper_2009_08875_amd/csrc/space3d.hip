@@ -348,16 +348,22 @@ __global__ __launch_bounds__(kLane) void prolong_add3_kernel(const T* __restrict
     const T* ee = e + row * slab3_elems(l - 1);
     T* xr = x + row * slab3_elems(l);
     const int bb = L.j & 1, cc = L.k & 1, J = L.j >> 1, Kc = L.k >> 1;
-    auto at = [&](int I, int Jn, int Kn) -> T {
-      return (I >= 1 && I <= nc && Jn >= 1 && Jn <= nc && Kn >= 1 && Kn <= nc)
-                 ? ee[((int64_t)(Kn - 1) * nc + (Jn - 1)) * pc + pos3(I, lc)]
-                 : T(0);
+    // slab index of coarse node (I, Jn, Kn), -1 outside the grid
+    auto idx = [&](int I, int Jn, int Kn) -> int64_t {
+      const bool in = I >= 1 && I <= nc && Jn >= 1 && Jn <= nc && Kn >= 1 && Kn <= nc;
+      return in ? ((int64_t)(Kn - 1) * nc + (Jn - 1)) * pc + pos3(I, lc) : -1;
     };
     FOR_NODES(L) {
       const int aa = i & 1, I = i >> 1;
-      T v = at(I, J, Kc);
-      if (aa | bb | cc) v = T(0.5) * (v + at(I + aa, J + bb, Kc + cc));
-      xr[L.off + p] += v;
+      const int64_t q0 = idx(I, J, Kc), q1 = idx(I + aa, J + bb, Kc + cc);
+      // the three loads are issued before any value is used: an end outside
+      // the grid loads element 0 and is then replaced by zero.  A node on a
+      // coarse node has q1 = q0, and the mean of a value with itself is that
+      // value exactly, so every node takes the same branch-free form.
+      const T e0 = ee[q0 < 0 ? 0 : q0], e1 = ee[q1 < 0 ? 0 : q1];
+      const T xo = xr[L.off + p];
+      const T v = T(0.5) * ((q0 < 0 ? T(0) : e0) + (q1 < 0 ? T(0) : e1));
+      xr[L.off + p] = xo + v;
     }
   }
 }
