@@ -318,23 +318,38 @@ __global__ __launch_bounds__(kLane) void residual3_kernel(const T* __restrict__ 
 template <typename T>
 __global__ __launch_bounds__(kLane) void restrict3_kernel(const T* __restrict__ r,
                                                           T* __restrict__ bc, int l, int rows) {
-  const int lc = l - 1;
-  FOR_LINE_ROWS(lc, rows) {
-    Line3 Lf;
-    Lf.n = grid_n(l);
-    Lf.pitch = line_pitch(l);
-    Lf.l = l;
-    Lf.j = 2 * L.j;
-    Lf.k = 2 * L.k;
-    Lf.off = ((int64_t)(Lf.k - 1) * Lf.n + (Lf.j - 1)) * Lf.pitch;
+  // coarse lines shorter than a wave share it: 64 / pitch lines per wave, one
+  // lane per slot (a line of 64 slots or more takes a wave to itself)
+  const int lc = l - 1, nc = grid_n(lc), pc = line_pitch(lc);
+  const int per = pc >= kLane ? 1 : kLane / pc;
+  const int p0 = per > 1 ? (int)threadIdx.x % pc : (int)threadIdx.x;
+  const int pstep = per > 1 ? pc : kLane;
+  const int line = blockIdx.x * per + (per > 1 ? (int)threadIdx.x / pc : 0);
+  if (line >= nc * nc) return;
+  const Line3 L = line3(line, lc);
+  Line3 Lf;
+  Lf.n = grid_n(l);
+  Lf.pitch = line_pitch(l);
+  Lf.l = l;
+  Lf.j = 2 * L.j;
+  Lf.k = 2 * L.k;
+  Lf.off = ((int64_t)(Lf.k - 1) * Lf.n + (Lf.j - 1)) * Lf.pitch;
+  const int64_t used = (int64_t)nc * nc * pc;
+  for (int row = blockIdx.y; row < rows; row += gridDim.y) {
     const T* rr = r + row * slab3_elems(l);
     T* o = bc + row * slab3_elems(lc);
-    FOR_NODES(L) {
-      const int f = 2 * i;  // the fine node under coarse node i
-      const T half = (axis_sum(rr, Lf, f) + face_sum(rr, Lf, f)) + body_sum(rr, Lf, f);
-      o[L.off + p] = nb3<T, 0, 0, 0>(rr, Lf, f) + T(0.5) * half;
+    for (int p = p0; p < pc; p += pstep) {
+      const int i = node_at3(p, lc);
+      if (i >= 1 && i <= nc) {
+        const int f = 2 * i;  // the fine node under coarse node i
+        const T half = (axis_sum(rr, Lf, f) + face_sum(rr, Lf, f)) + body_sum(rr, Lf, f);
+        o[L.off + p] = nb3<T, 0, 0, 0>(rr, Lf, f) + T(0.5) * half;
+      } else {
+        o[L.off + p] = T(0);  // the line's pad
+      }
     }
-    zero_pads(o, L, lc, blockIdx.x);
+    if (line == nc * nc - 1)  // the slab's tail
+      for (int64_t e = used + p0; e < slab3_elems(lc); e += pstep) o[e] = T(0);
   }
 }
 
@@ -638,7 +653,11 @@ hipError_t vcycle3(hipStream_t s, const Mg3Work<T>& w, T* x, const T* b, int l, 
     residual3_kernel<T, true><<<g, kLane, 0, s>>>(x, b, w.r[l], l, rows, a, sigma);
   else
     residual3_kernel<T, false><<<g, kLane, 0, s>>>(x, b, w.r[l], l, rows, a, sigma);
-  restrict3_kernel<T><<<grid3(l - 1, rows), kLane, 0, s>>>(w.r[l], w.b[l - 1], l, rows);
+  {
+    const int nc = grid_n(l - 1), pc = line_pitch(l - 1), rp = pc >= kLane ? 1 : kLane / pc;
+    const dim3 gc((unsigned)((nc * nc + rp - 1) / rp), (unsigned)std::min(rows, kMaxGridRows));
+    restrict3_kernel<T><<<gc, kLane, 0, s>>>(w.r[l], w.b[l - 1], l, rows);
+  }
   if (l - 1 <= kCoarse3) {
     // levels l - 1 .. 1 from zero in one launch, every level in LDS
     const hipError_t e =
