@@ -19,8 +19,9 @@
 //
 // Kernels run one 64-lane wave per grid line (j, k) and time row (a
 // grid-stride loop over the rows); the Gauss-Seidel launches put 64 / Q lines
-// in one wave on levels below 8, one lane per node of the colour.  Neighbour values come straight from
-// global memory, which the L2 caches; there is no LDS tiling as in the
+// in one wave on levels below 8, one lane per node of the colour, and the
+// residual, restriction and prolongation launches put 64 / pitch lines in one
+// wave on levels below 6.  Neighbour values come straight from global memory, which the L2 caches; there is no LDS tiling as in the
 // two-dimensional kernels.  Levels 4..1 of a V-cycle run in one launch with one
 // workgroup per time row and every level in LDS (mg3_coarse_kernel).
 //
@@ -138,6 +139,26 @@ inline dim3 grid3(int l, int rows) {
 // lanes over the slots of the line; i: the slot's node, skipped at the pad
 #define FOR_NODES(L)                                                   \
   for (int p = threadIdx.x; p < (L).pitch; p += kLane)                 \
+    if (const int i = node_at3(p, (L).l); i >= 1 && i <= (L).n)
+
+// Packed lines: lines shorter than a wave share it (64 / pitch lines per
+// wave, one lane per slot); a line of 64 slots or more takes a wave to
+// itself, its lanes striding over the slots.  grid3p is the matching grid.
+struct Packed {
+  int line, p0, pstep;
+};
+__device__ __forceinline__ Packed packed_line(int l) {
+  const int pitch = line_pitch(l);
+  if (pitch >= kLane) return {(int)blockIdx.x, (int)threadIdx.x, kLane};
+  return {(int)blockIdx.x * (kLane / pitch) + (int)threadIdx.x / pitch,
+          (int)threadIdx.x % pitch, pitch};
+}
+inline dim3 grid3p(int l, int rows) {
+  const int n = grid_n(l), pitch = line_pitch(l), per = pitch >= kLane ? 1 : kLane / pitch;
+  return dim3((unsigned)((n * n + per - 1) / per), (unsigned)std::min(rows, kMaxGridRows));
+}
+#define FOR_PACKED_NODES(L, pk)                                        \
+  for (int p = (pk).p0; p < (L).pitch; p += (pk).pstep)                \
     if (const int i = node_at3(p, (L).l); i >= 1 && i <= (L).n)
 
 // writes the pad of a line and the slab tail zero
@@ -301,12 +322,15 @@ __global__ __launch_bounds__(kLane) void residual3_kernel(const T* __restrict__ 
                                                           T* __restrict__ r, int l, int rows,
                                                           double a,
                                                           const double* __restrict__ sigma) {
-  FOR_LINE_ROWS(l, rows) {
+  const Packed pk = packed_line(l);
+  if (pk.line >= grid_n(l) * grid_n(l)) return;
+  const Line3 L = line3(pk.line, l);
+  for (int row = blockIdx.y; row < rows; row += gridDim.y) {
     const C3 c = coef3(a, sigma ? sigma[row] : 0.0, l);
     const T* xr = x + row * slab3_elems(l);
     const T* br = b + row * slab3_elems(l);
     T* rr = r + row * slab3_elems(l);
-    FOR_NODES(L)
+    FOR_PACKED_NODES(L, pk)
       rr[L.off + p] = br[L.off + p] - (T(c.c0) * nb3<T, 0, 0, 0>(xr, L, i) +
                                        off3<T, DIAG>(xr, L, i, c));
   }
@@ -318,14 +342,10 @@ __global__ __launch_bounds__(kLane) void residual3_kernel(const T* __restrict__ 
 template <typename T>
 __global__ __launch_bounds__(kLane) void restrict3_kernel(const T* __restrict__ r,
                                                           T* __restrict__ bc, int l, int rows) {
-  // coarse lines shorter than a wave share it: 64 / pitch lines per wave, one
-  // lane per slot (a line of 64 slots or more takes a wave to itself)
   const int lc = l - 1, nc = grid_n(lc), pc = line_pitch(lc);
-  const int per = pc >= kLane ? 1 : kLane / pc;
-  const int p0 = per > 1 ? (int)threadIdx.x % pc : (int)threadIdx.x;
-  const int pstep = per > 1 ? pc : kLane;
-  const int line = blockIdx.x * per + (per > 1 ? (int)threadIdx.x / pc : 0);
-  if (line >= nc * nc) return;
+  const Packed pk = packed_line(lc);
+  if (pk.line >= nc * nc) return;
+  const int line = pk.line, p0 = pk.p0, pstep = pk.pstep;
   const Line3 L = line3(line, lc);
   Line3 Lf;
   Lf.n = grid_n(l);
@@ -358,7 +378,10 @@ __global__ __launch_bounds__(kLane) void restrict3_kernel(const T* __restrict__ 
 template <typename T>
 __global__ __launch_bounds__(kLane) void prolong_add3_kernel(const T* __restrict__ e,
                                                              T* __restrict__ x, int l, int rows) {
-  FOR_LINE_ROWS(l, rows) {
+  const Packed pk = packed_line(l);
+  if (pk.line >= grid_n(l) * grid_n(l)) return;
+  const Line3 L = line3(pk.line, l);
+  for (int row = blockIdx.y; row < rows; row += gridDim.y) {
     const int nc = grid_n(l - 1), pc = line_pitch(l - 1), lc = l - 1;
     const T* ee = e + row * slab3_elems(l - 1);
     T* xr = x + row * slab3_elems(l);
@@ -368,7 +391,7 @@ __global__ __launch_bounds__(kLane) void prolong_add3_kernel(const T* __restrict
       const bool in = I >= 1 && I <= nc && Jn >= 1 && Jn <= nc && Kn >= 1 && Kn <= nc;
       return in ? ((int64_t)(Kn - 1) * nc + (Jn - 1)) * pc + pos3(I, lc) : -1;
     };
-    FOR_NODES(L) {
+    FOR_PACKED_NODES(L, pk) {
       const int aa = i & 1, I = i >> 1;
       const int64_t q0 = idx(I, J, Kc), q1 = idx(I + aa, J + bb, Kc + cc);
       // the three loads are issued before any value is used: an end outside
@@ -637,7 +660,7 @@ hipError_t combine3(hipStream_t s, const T* z1, const T* z2, const T* extra, int
 template <typename T>
 hipError_t vcycle3(hipStream_t s, const Mg3Work<T>& w, T* x, const T* b, int l, int rows,
                    double a, const double* sigma) {
-  const dim3 g = grid3(l, rows);
+  const dim3 g = grid3p(l, rows);  // residual, prolongation
   // Gauss-Seidel launches: 64 / Q lines per wave (l >= 2; l is at least 2 here)
   const int n = grid_n(l), per = kLane / (1 << (l - 2));
   const dim3 gr((unsigned)((n * n + per - 1) / per), (unsigned)std::min(rows, kMaxGridRows));
@@ -653,11 +676,7 @@ hipError_t vcycle3(hipStream_t s, const Mg3Work<T>& w, T* x, const T* b, int l, 
     residual3_kernel<T, true><<<g, kLane, 0, s>>>(x, b, w.r[l], l, rows, a, sigma);
   else
     residual3_kernel<T, false><<<g, kLane, 0, s>>>(x, b, w.r[l], l, rows, a, sigma);
-  {
-    const int nc = grid_n(l - 1), pc = line_pitch(l - 1), rp = pc >= kLane ? 1 : kLane / pc;
-    const dim3 gc((unsigned)((nc * nc + rp - 1) / rp), (unsigned)std::min(rows, kMaxGridRows));
-    restrict3_kernel<T><<<gc, kLane, 0, s>>>(w.r[l], w.b[l - 1], l, rows);
-  }
+  restrict3_kernel<T><<<grid3p(l - 1, rows), kLane, 0, s>>>(w.r[l], w.b[l - 1], l, rows);
   if (l - 1 <= kCoarse3) {
     // levels l - 1 .. 1 from zero in one launch, every level in LDS
     const hipError_t e =
