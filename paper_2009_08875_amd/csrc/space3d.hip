@@ -290,6 +290,24 @@ __global__ __launch_bounds__(kLane) void combine3_kernel(const T* __restrict__ z
   }
 }
 
+// XCD-aware order of the Gauss-Seidel tiles.  Workgroups are dealt to the 8
+// XCDs in turn in the order of their linear index, and each XCD has its own
+// L2.  The linear index is renumbered so that each XCD takes one contiguous
+// range of (line group, row) tiles: the lines next to a tile (j +- 1, k +- 1)
+// are then mostly ones its own L2 has just fetched.  A bijection of the grid
+// onto itself.
+struct Tile {
+  int x, y;
+};
+__device__ __forceinline__ Tile xcd_tile() {
+  constexpr int kXcd = 8;
+  const int64_t gx = gridDim.x, total = gx * gridDim.y;
+  const int64_t id = (int64_t)blockIdx.y * gx + blockIdx.x;
+  const int64_t per = total / kXcd, rem = total % kXcd, x = id % kXcd;
+  const int64_t t = x * per + (x < rem ? x : rem) + id / kXcd;
+  return {(int)(t % gx), (int)(t / gx)};
+}
+
 // One colour of Gauss-Seidel on level l >= 2 for C = a A + sigma_row M.  A
 // wave takes 64 / Q lines (Q = 2^(l-2) slots per segment, at most 64) and
 // one lane per slot of each line's colour segment: line (j, k) holds colour
@@ -300,7 +318,8 @@ __global__ __launch_bounds__(kLane) void relax3_kernel(T* __restrict__ x,
                                                        double a, const double* __restrict__ sigma,
                                                        int colour) {
   const int n = grid_n(l), Q = 1 << (l - 2);
-  const int line = blockIdx.x * (kLane / Q) + threadIdx.x / Q;
+  const Tile tile = xcd_tile();
+  const int line = tile.x * (kLane / Q) + threadIdx.x / Q;
   const int q = threadIdx.x & (Q - 1);
   if (line >= n * n) return;
   const Line3 L = line3(line, l);
@@ -308,7 +327,7 @@ __global__ __launch_bounds__(kLane) void relax3_kernel(T* __restrict__ x,
   const int i = 4 * q + r;
   if (i < 1 || i > n) return;
   const int64_t at = L.off + r * Q + q;
-  for (int row = blockIdx.y; row < rows; row += gridDim.y) {
+  for (int row = tile.y; row < rows; row += gridDim.y) {
     const C3 c = coef3(a, sigma ? sigma[row] : 0.0, l);
     T* xr = x + row * slab3_elems(l);
     const T* br = b + row * slab3_elems(l);
